@@ -1,0 +1,217 @@
+"""Throughput of the fused two-component Shan-Chen D3Q19 step on one MI355X.
+
+Workload: the 1 % mixture in packed spheres -- a 256^3 periodic lattice
+filled with seeded non-overlapping spheres of radius 12 at porosity 0.40
+(solid mask), droplets of component A (radius 4, 1 % of the pore volume) in
+a carrier B with droplet interfaces of tanh width 1.5; nu_B = 1/6,
+nu_A = 1/60 (ratio 10); G = -4.2; body force 1e-6 along z; wall parameter
+rho^s = 0.25.  A step is one launch of the fused
+kernel over the whole lattice (pull-stream with bounce-back, moments, LDS
+pseudo-potential halo, Shan-Chen force, regularized collision with the
+forcing term), with the FP64 mass / finiteness check every 100 steps.
+
+MLUPS counts fluid-site updates (solid sites hold no populations and are
+skipped).  Algorithmic bytes per update: 2 components x 19 populations x
+(read + write) x storage size = 304 B at FP32.  The printed JSON line gives
+FP32 as `value`; FP64, FP16-shifted and BF16-shifted storage are measured
+the same way under `precisions`.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS and % HBM peak (FP32 vs FP16-shifted); time-to-steady-state w/ warm start"
+KERNEL_SRC = os.path.join(ROOT, "paper_1711_03254_amd", "csrc", "lbm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_fp32_packed_spheres_256.json")
+
+
+def workload(n=256, G=-4.2, width=1.5):
+    from paper_1711_03254_amd import inputs
+    solid, rA, rB, info = inputs.packed_spheres_case(n=n, radius=12.0, porosity=0.40, drop_radius=4.0,
+                                                     drop_fraction=0.01, seed=3, minority=0.03,
+                                                     interface_width=width)
+    rA[solid == 1] = 0.0
+    rB[solid == 1] = 0.0
+    phys = dict(tau=(1.0 / 60.0 / (1.0 / 3.0) + 0.5, 1.0), G=G, g=(0.0, 0.0, 1e-6), rho_s=0.25)
+    return solid, rA, rB, info, phys
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def time_precision(lbm, torch, prec, solid, rA, rB, phys, steps, warmup, check_every):
+    stream = torch.cuda.current_stream()
+    n = solid.shape[0]
+    ctx = lbm.lbm_init(lbm.Params(n, n, n, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(rA, rB),
+                                  check_every=check_every, stream=stream, **phys))
+    info = lbm.lbm_info(ctx)
+    lbm.lbm_step(ctx, warmup)
+    torch.cuda.synchronize()
+    # (1) the whole step as a user runs it, periodic checks included
+    t0 = time.perf_counter()
+    lbm.lbm_step(ctx, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # (2) the step kernel alone: HIP events on the stream the kernel runs on
+    ctx2 = lbm.lbm_init(lbm.Params(n, n, n, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(rA, rB),
+                                   check_every=0, stream=stream, **phys))
+    lbm.lbm_step(ctx2, warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lbm.lbm_step(ctx2, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = e0.elapsed_time(e1) / steps
+    red = lbm.lbm_reduce(ctx)
+    drift = [abs(red[k] - info["mass0"][k]) / info["mass0"][k] for k in range(2)]
+    lbm.lbm_free(ctx)
+    lbm.lbm_free(ctx2)
+    nf = info["n_fluid"]
+    bpl = info["bytes_per_lu"]
+    ms_step = wall / steps * 1e3
+    return {
+        "mlups": nf / (ms_step * 1e-3) / 1e6,
+        "ms_per_step": ms_step,
+        "kernel_ms": kern_ms,
+        "kernel_mlups": nf / (kern_ms * 1e-3) / 1e6,
+        "bytes_per_lu": bpl,
+        "algorithmic_GBs": nf * bpl / (kern_ms * 1e-3) / 1e9,
+        "hbm_frac": nf * bpl / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "mass_drift": max(drift),
+        "n_fluid": nf,
+        "tile": list(info["tile"]),
+        "zchunk": info["zchunk"],
+        "blocks": info["blocks"],
+    }
+
+
+def cpu_baseline(solid, rA, rB, phys, steps=3):
+    """The FP64 oracle on the same lattice, timed on the host's cores."""
+    from oracle import oracle as ora
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    threads = min(threads, 16)
+    ora.set_threads(threads)
+    n = solid.shape[0]
+    p = ora.Params(n, n, n, solid=solid, **phys)
+    f = ora.init(p, rA, rB)
+    t0 = time.perf_counter()
+    ora.run(p, f, steps)
+    dt = time.perf_counter() - t0
+    nf = int((solid == 0).sum())
+    return {"value": nf * steps / dt / 1e6, "unit": "MLUPS", "cores": ora.get_threads(), "kind": "oracle",
+            "sample": f"the full {n}^3 workload, {steps} steps of the FP64 oracle ({dt:.1f} s)"}
+
+
+def traffic_for(kern_ms_unused, n_fluid):
+    """HBM bytes per step launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE))
+    if t.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precisions", default="fp32,fp16s,bf16s,fp64")
+    ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--G", type=float, default=-4.2)
+    ap.add_argument("--interface-width", type=float, default=1.5)
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="also run a plain device copy of this many GiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the step is measured on a single "
+              "MI355X; multi-GPU execution is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1711_03254_amd.lbm as lbm
+    lbm.load_library()
+    torch.cuda.set_device(0)
+
+    if args.copy_probe_gib > 0:
+        nel = int(args.copy_probe_gib * 2 ** 30 / 4)
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: 3 copies of {nel * 4} bytes", file=sys.stderr, flush=True)
+        del src, dst
+
+    solid, rA, rB, info, phys = workload(args.size, args.G, args.interface_width)
+    print(f"# workload ready: {info}", file=sys.stderr, flush=True)
+    res = {}
+    for prec in args.precisions.split(","):
+        k = args.steps if prec == "fp32" else max(50, args.steps // 2)
+        res[prec] = time_precision(lbm, torch, prec, solid, rA, rB, phys, k, args.warmup, args.check_every)
+        print(f"# {prec}: {json.dumps(res[prec])}", file=sys.stderr, flush=True)
+    main_r = res["fp32"]
+    n_fluid = main_r["n_fluid"]
+    roof = {
+        "bound": "hbm",
+        "achieved": round(main_r["algorithmic_GBs"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(main_r["algorithmic_GBs"] / HBM_PEAK_GBS, 4),
+        "traffic": traffic_for(main_r["kernel_ms"], n_fluid),
+        "kernel": "step_kernel<float,64,4,MODE_STEP>",
+        "algorithmic_bytes_per_launch": n_fluid * main_r["bytes_per_lu"],
+        "kernel_ms": round(main_r["kernel_ms"], 4),
+    }
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(solid, rA, rB, phys)
+        print(f"# cpu baseline: {cpu}", file=sys.stderr, flush=True)
+    line = {
+        "metric": METRIC,
+        "value": round(main_r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"1% mixture in packed spheres, {args.size}^3 periodic, sphere radius 12, porosity "
+                        f"{info['porosity']:.3f}, {info['droplets']} droplets of A (radius 4, tanh interface "
+                        f"width {args.interface_width}), nu ratio 10, G={args.G}, g=1e-6 z, rho_s=0.25, "
+                        f"FP32 storage, FP64 check every {args.check_every} steps",
+            "n_fluid": n_fluid,
+            "parallelism": "single GPU",
+        },
+        "hbm_frac": round(main_r["hbm_frac"], 4),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "precisions": {k: {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()}
+                       for k, r in res.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

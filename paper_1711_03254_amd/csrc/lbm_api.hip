@@ -1,0 +1,741 @@
+// lbm_api.hip -- the C ABI declared in include/lbm.h: context lifecycle,
+// argument validation, launch configuration, the periodic FP64 mass check,
+// and the population / field exchange calls.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+
+struct lbm_ctx {
+    lbm_params p;               // copy; borrowed pointers cleared
+    int64_t N = 0, plane = 0, nfluid = 0;
+    size_t esz = 0;
+    void *f[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint32_t *links = nullptr;
+    double *partials = nullptr;
+    double *red_dev = nullptr;
+    double *red_host = nullptr;   // pinned
+    double *stage = nullptr;      // 5N doubles, allocated on first use
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    double mass0[2] = {0, 0};
+    double ref[2] = {0, 0};       // shift references of 16-bit storage (0 for FP32 / FP64)
+    bool ref_set = false;
+    int64_t steps_done = 0;
+    int tile_x = 0, tile_y = 0, zchunk = 0, ntx = 0, nty = 0, nzc = 0;
+    // replayable graphs of kGraphSteps plain steps, one per starting buffer
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool graphs_off = false;
+    std::string err;
+};
+
+struct lbm_batch {
+    std::vector<lbm_ctx *> ctx;
+    int prec = 0, tile_x = 0, tile_y = 0;
+    hipStream_t stream = nullptr;
+    size_t desc_size = 0;
+    std::vector<char> descs_host;
+    void *descs_dev = nullptr;
+    int2 *work_dev = nullptr;
+    int nwork = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graphs_off = false;
+    std::string err;
+};
+
+namespace {
+
+// Plain steps per captured graph (even, so a replay returns to the buffer it
+// started from).
+constexpr int kGraphSteps = 16;
+
+std::string g_init_error = "no error";
+
+int fail(lbm_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    else g_init_error = msg;
+    return code;
+}
+
+int bfail(lbm_batch *b, int code, const std::string &msg) {
+    if (b) b->err = msg;
+    else g_init_error = msg;
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((c), LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t storage_bytes(int prec) {
+    switch (prec) {
+    case LBM_FP64: return 8;
+    case LBM_FP32: return 4;
+    case LBM_FP16S:
+    case LBM_BF16S: return 2;
+    default: return 0;
+    }
+}
+
+double default_mass_tol(int prec) {
+    switch (prec) {
+    case LBM_FP64: return 1e-9;
+    case LBM_FP32: return 1e-3;
+    default: return 1e-1;
+    }
+}
+
+void choose_launch(lbm_ctx *c) {
+    const lbm_params &p = c->p;
+    int tx = p.tile_x, ty = p.tile_y;
+    if (tx == 0 || ty == 0) {
+        if (p.nx >= 48) { tx = 64; ty = 4; }
+        else if (p.nx >= 24) { tx = 32; ty = 8; }
+        else if (p.nx >= 12) { tx = 16; ty = 16; }
+        else { tx = 8; ty = 32; }
+    }
+    c->tile_x = tx;
+    c->tile_y = ty;
+    c->ntx = (p.nx + tx - 1) / tx;
+    c->nty = (p.ny + ty - 1) / ty;
+    int zc = p.zchunk;
+    if (zc <= 0) {
+        // Aim at about 2048 blocks (8 per CU) with chunks of at least 4 planes.
+        const int64_t xy = (int64_t)c->ntx * c->nty;
+        const int64_t want = (2048 + xy - 1) / xy;
+        zc = (int)((p.nz + want - 1) / want);
+        if (zc < 4) zc = 4;
+    }
+    if (zc > p.nz) zc = p.nz;
+    c->zchunk = zc;
+    c->nzc = (p.nz + zc - 1) / zc;
+}
+
+lbm::StepLaunch make_launch(const lbm_ctx *c, const void *src, void *dst) {
+    const lbm_params &p = c->p;
+    lbm::StepLaunch L{};
+    L.src = src;
+    L.dst = dst;
+    L.links = c->links;
+    L.nx = p.nx; L.ny = p.ny; L.nz = p.nz;
+    L.plane = c->plane;
+    L.tile_x = c->tile_x; L.tile_y = c->tile_y; L.zchunk = c->zchunk;
+    L.ntx = c->ntx; L.nty = c->nty; L.nzc = c->nzc;
+    L.tau0 = p.tau[0]; L.tau1 = p.tau[1]; L.G = p.G;
+    L.gx = p.g[0]; L.gy = p.g[1]; L.gz = p.g[2];
+    L.wall0 = p.rho_s < 0 ? -p.rho_s : 0.0;   // rho^s_1 = -rho^s Theta(-rho^s)
+    L.wall1 = p.rho_s > 0 ? p.rho_s : 0.0;    // rho^s_2 =  rho^s Theta(rho^s)
+    L.ref0 = c->ref[0];
+    L.ref1 = c->ref[1];
+    L.eq_kind = p.eq_kind; L.force_kind = p.force_kind;
+    L.partials = c->partials;
+    return L;
+}
+
+int nblocks(const lbm_ctx *c) { return c->ntx * c->nty * c->nzc; }
+
+// FP64 sums of the current state into c->red_host (synchronizes).
+int measure(lbm_ctx *c, double *rho0, double *rho1, double *u) {
+    lbm::StepLaunch L = make_launch(c, c->f[c->cur], nullptr);
+    L.out_rho0 = rho0; L.out_rho1 = rho1; L.out_u = u;
+    HIPCHK(c, lbm::launch_step(c->p.prec, lbm::MODE_MOMENTS, L, c->stream));
+    HIPCHK(c, lbm::launch_finalize(c->partials, nblocks(c), c->red_dev, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->red_host, c->red_dev, sizeof(double) * lbm::kPartialStride,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int ensure_stage(lbm_ctx *c) {
+    if (c->stage) return LBM_OK;
+    if (hipMalloc(&c->stage, sizeof(double) * 5 * (size_t)c->N) != hipSuccess) {
+        c->stage = nullptr;
+        (void)hipGetLastError();
+        return fail(c, LBM_ENOMEM, "cannot allocate the 5N-double staging buffer");
+    }
+    return LBM_OK;
+}
+
+int validate_fields(lbm_ctx *c, const uint8_t *solid_h, const double *r0, const double *r1, const double *u,
+                    int64_t *nfluid) {
+    int64_t nf = 0;
+    for (int64_t s = 0; s < c->N; ++s) {
+        if (solid_h && solid_h[s]) continue;
+        ++nf;
+        const double a = r0[s], b = r1[s];
+        if (!std::isfinite(a) || !std::isfinite(b) || a < 0 || b < 0 || a + b <= 0) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "invalid densities at fluid site %lld: rho1=%g rho2=%g (need >= 0, sum > 0)",
+                          (long long)s, a, b);
+            return fail(c, LBM_EINVAL, buf);
+        }
+        if (u && !(std::isfinite(u[s]) && std::isfinite(u[c->N + s]) && std::isfinite(u[2 * c->N + s])))
+            return fail(c, LBM_EINVAL, "non-finite initial velocity");
+    }
+    if (nf == 0) return fail(c, LBM_EINVAL, "the lattice has no fluid site");
+    *nfluid = nf;
+    return LBM_OK;
+}
+
+// Copies the field arrays to the device staging buffer (when they are on
+// the host), validates them, and sets the state to their equilibrium.
+int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u, int on_device) {
+    const size_t NB = sizeof(double) * (size_t)c->N;
+    std::vector<double> h0, h1, hu;
+    std::vector<uint8_t> hs;
+    const double *vr0 = r0, *vr1 = r1, *vu = u;
+    if (on_device) {
+        h0.resize(c->N); h1.resize(c->N);
+        HIPCHK(c, hipMemcpy(h0.data(), r0, NB, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(h1.data(), r1, NB, hipMemcpyDeviceToHost));
+        vr0 = h0.data(); vr1 = h1.data();
+        if (u) {
+            hu.resize(3 * c->N);
+            HIPCHK(c, hipMemcpy(hu.data(), u, 3 * NB, hipMemcpyDeviceToHost));
+            vu = hu.data();
+        }
+    }
+    // solid mask back from the links (bit 0)
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<uint32_t> lk(c->N);
+    HIPCHK(c, hipMemcpy(lk.data(), c->links, sizeof(uint32_t) * c->N, hipMemcpyDeviceToHost));
+    hs.resize(c->N);
+    for (int64_t s = 0; s < c->N; ++s) hs[s] = (uint8_t)(lk[s] & 1u);
+    int64_t nf = 0;
+    int rc = validate_fields(c, hs.data(), vr0, vr1, vu, &nf);
+    if (rc) return rc;
+    c->nfluid = nf;
+    if (!c->ref_set) {
+        // 16-bit storage: shift by w_i * rho_ref[a]; default = the mean initial density of the
+        // component over fluid sites (the deviations stay small where a component is in its usual phase).
+        const bool shifted = c->p.prec == LBM_FP16S || c->p.prec == LBM_BF16S;
+        for (int a = 0; a < 2; ++a) {
+            const double *r = a == 0 ? vr0 : vr1;
+            double mean = 0.0;
+            for (int64_t s = 0; s < c->N; ++s)
+                if (!hs[s]) mean += r[s];
+            mean /= (double)nf;
+            const double want = c->p.rho_ref[a];
+            c->ref[a] = !shifted ? 0.0 : (want > 0 ? want : (want < 0 ? 0.0 : mean));
+        }
+        c->ref_set = true;
+    }
+    rc = ensure_stage(c);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->stage, vr0, NB, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->stage + c->N, vr1, NB, hipMemcpyHostToDevice, c->stream));
+    if (vu) HIPCHK(c, hipMemcpyAsync(c->stage + 2 * c->N, vu, 3 * NB, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, lbm::launch_init_fields(c->p.prec, c->f[c->cur], c->links, c->stage, c->stage + c->N,
+                                      vu ? c->stage + 2 * c->N : nullptr, c->p.nx, c->p.ny, c->p.nz, c->plane,
+                                      c->p.eq_kind, c->ref, c->stream));
+    rc = measure(c, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    c->mass0[0] = c->red_host[0];
+    c->mass0[1] = c->red_host[1];
+    return LBM_OK;
+}
+
+void release(lbm_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (void *q : {c->f[0], c->f[1], (void *)c->links, (void *)c->partials, (void *)c->red_dev, (void *)c->stage})
+        if (q) (void)hipFree(q);
+    if (c->red_host) (void)hipHostFree(c->red_host);
+    for (int k = 0; k < 2; ++k) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    }
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_init(const lbm_params *pin, lbm_ctx **out) {
+    if (!out) return fail(nullptr, LBM_EINVAL, "lbm_init: out is NULL");
+    *out = nullptr;
+    if (!pin) return fail(nullptr, LBM_EINVAL, "lbm_init: params is NULL");
+    const lbm_params &p = *pin;
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(nullptr, LBM_EINVAL, "lattice dimensions must be >= 1");
+    const size_t esz = storage_bytes(p.prec);
+    if (!esz) return fail(nullptr, LBM_EINVAL, "unknown precision");
+    for (int k = 0; k < 2; ++k)
+        if (!(p.tau[k] > 0.5) || !std::isfinite(p.tau[k]))
+            return fail(nullptr, LBM_EINVAL, "tau must be finite and > 1/2 (nu > 0)");
+    if (!std::isfinite(p.G) || !std::isfinite(p.g[0]) || !std::isfinite(p.g[1]) || !std::isfinite(p.g[2]) ||
+        !std::isfinite(p.rho_s))
+        return fail(nullptr, LBM_EINVAL, "G, g and rho_s must be finite");
+    if (p.eq_kind != 0 && p.eq_kind != 1) return fail(nullptr, LBM_EINVAL, "eq_kind must be 0 or 1");
+    if (p.force_kind != 0 && p.force_kind != 1) return fail(nullptr, LBM_EINVAL, "force_kind must be 0 or 1");
+    if (p.check_every < 0) return fail(nullptr, LBM_EINVAL, "check_every must be >= 0");
+    if (!(p.mass_tol >= 0) || !std::isfinite(p.rho_ref[0]) || !std::isfinite(p.rho_ref[1]))
+        return fail(nullptr, LBM_EINVAL, "mass_tol must be >= 0 and rho_ref finite");
+    if (!p.rho_init[0] || !p.rho_init[1]) return fail(nullptr, LBM_EINVAL, "rho_init pointers are NULL");
+    if ((p.tile_x || p.tile_y) && !lbm::tile_supported(p.tile_x, p.tile_y))
+        return fail(nullptr, LBM_EINVAL, "unsupported tile (64x4, 32x8, 16x16 or 8x32)");
+    if (p.zchunk < 0) return fail(nullptr, LBM_EINVAL, "zchunk must be >= 0");
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_ENOMEM, "cannot allocate the context");
+    c->p = p;
+    c->p.solid = nullptr;
+    c->p.rho_init[0] = c->p.rho_init[1] = nullptr;
+    c->p.u_init = nullptr;
+    if (c->p.mass_tol == 0) c->p.mass_tol = default_mass_tol(p.prec);
+    c->N = (int64_t)p.nx * p.ny * p.nz;
+    c->esz = esz;
+    c->plane = (c->N + 127) / 128 * 128;   // each plane starts 256-byte aligned
+    if (2 * (uint64_t)c->plane * esz >= (1ull << 32)) {
+        int rc = fail(nullptr, LBM_EINVAL, "lattice too large: one population plane must stay below 2 GiB");
+        delete c;
+        return rc;
+    }
+    choose_launch(c);
+
+    auto bail = [&](int rc) {
+        g_init_error = c->err;
+        release(c);
+        return rc;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(c, LBM_EDEVICE, "no HIP device"));
+    if (p.stream) c->stream = static_cast<hipStream_t>(p.stream);
+    else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(c, LBM_EDEVICE, "hipStreamCreate failed"));
+        c->own_stream = true;
+    }
+    const size_t fbytes = (size_t)2 * 19 * c->plane * esz;
+    for (int k = 0; k < 2; ++k) {
+        if (hipMalloc(&c->f[k], fbytes) != hipSuccess) {
+            c->f[k] = nullptr;
+            return bail(fail(c, LBM_ENOMEM, "cannot allocate the population buffers"));
+        }
+        if (hipMemsetAsync(c->f[k], 0, fbytes, c->stream) != hipSuccess)
+            return bail(fail(c, LBM_EDEVICE, "hipMemset failed"));
+    }
+    if (hipMalloc(&c->links, sizeof(uint32_t) * c->N) != hipSuccess ||
+        hipMalloc(&c->partials, sizeof(double) * lbm::kPartialStride * nblocks(c)) != hipSuccess ||
+        hipMalloc(&c->red_dev, sizeof(double) * lbm::kPartialStride) != hipSuccess ||
+        hipHostMalloc(&c->red_host, sizeof(double) * lbm::kPartialStride, hipHostMallocDefault) != hipSuccess)
+        return bail(fail(c, LBM_ENOMEM, "cannot allocate the link mask or reduction buffers"));
+
+    // Solid mask -> link mask.
+    uint8_t *solid_d = nullptr;
+    if (p.solid) {
+        if (hipMalloc(&solid_d, c->N) != hipSuccess) return bail(fail(c, LBM_ENOMEM, "cannot stage the solid mask"));
+        hipError_t e = hipMemcpyAsync(solid_d, p.solid, c->N,
+                                      p.inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = lbm::launch_links(solid_d, c->links, p.nx, p.ny, p.nz, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(solid_d);
+        if (e != hipSuccess) return bail(fail(c, LBM_EDEVICE, std::string("link mask: ") + hipGetErrorString(e)));
+    } else {
+        hipError_t e = lbm::launch_links(nullptr, c->links, p.nx, p.ny, p.nz, c->stream);
+        if (e != hipSuccess) return bail(fail(c, LBM_EDEVICE, std::string("link mask: ") + hipGetErrorString(e)));
+    }
+    int rc = load_fields(c, p.rho_init[0], p.rho_init[1], p.u_init, p.inputs_on_device);
+    if (rc) return bail(rc);
+    *out = c;
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Checks the FP64 sums of a MODE_CHECK step (already finalized into
+// c->red_dev and copied to c->red_host, stream synchronized).
+int evaluate_check(lbm_ctx *c) {
+    const double *r = c->red_host;
+    char buf[200];
+    if (r[5] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1])) {
+        std::snprintf(buf, sizeof buf, "non-finite state at step %lld (%g sites)", (long long)c->steps_done - 1, r[5]);
+        return fail(c, LBM_ENONFINITE, buf);
+    }
+    for (int a = 0; a < 2; ++a) {
+        const double ref = c->mass0[a];
+        const double drift = std::fabs(r[a] - ref) / (ref > 0 ? ref : 1.0);
+        if (drift > c->p.mass_tol) {
+            std::snprintf(buf, sizeof buf, "component %d mass drift %.3e > %.3e at step %lld", a + 1, drift,
+                          c->p.mass_tol, (long long)c->steps_done - 1);
+            return fail(c, LBM_EMASSDRIFT, buf);
+        }
+    }
+    return LBM_OK;
+}
+
+int64_t plain_steps_before_check(int64_t done, int every) {
+    if (every <= 0) return INT64_MAX;
+    return every - 1 - done % every;
+}
+
+// Captures kGraphSteps plain steps starting from buffer `parity`.
+bool capture_ctx_graph(lbm_ctx *c, int parity) {
+    if (c->graphs_off) return false;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        c->graphs_off = true;
+        return false;
+    }
+    hipError_t e = hipSuccess;
+    int cur = parity;
+    for (int j = 0; j < kGraphSteps && e == hipSuccess; ++j) {
+        lbm::StepLaunch L = make_launch(c, c->f[cur], c->f[1 - cur]);
+        e = lbm::launch_step(c->p.prec, lbm::MODE_STEP, L, c->stream);
+        cur = 1 - cur;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g ||
+        hipGraphInstantiate(&c->gexec[parity], g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        c->gexec[parity] = nullptr;
+        c->graphs_off = true;
+        return false;
+    }
+    c->graph[parity] = g;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_step(lbm_ctx *c, int64_t n) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "lbm_step: NULL context");
+    if (n < 0) return fail(c, LBM_EINVAL, "lbm_step: n < 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    int64_t k = 0;
+    while (k < n) {
+        int64_t plain = std::min(n - k, plain_steps_before_check(c->steps_done, c->p.check_every));
+        // runs of plain steps: replay the captured graph where it fits
+        while (plain >= kGraphSteps && (c->gexec[c->cur] || capture_ctx_graph(c, c->cur))) {
+            HIPCHK(c, hipGraphLaunch(c->gexec[c->cur], c->stream));
+            c->steps_done += kGraphSteps;
+            k += kGraphSteps;
+            plain -= kGraphSteps;
+        }
+        for (; plain > 0; --plain, ++k) {
+            lbm::StepLaunch L = make_launch(c, c->f[c->cur], c->f[1 - c->cur]);
+            HIPCHK(c, lbm::launch_step(c->p.prec, lbm::MODE_STEP, L, c->stream));
+            c->cur = 1 - c->cur;
+            c->steps_done++;
+        }
+        if (k < n) {  // a check step
+            lbm::StepLaunch L = make_launch(c, c->f[c->cur], c->f[1 - c->cur]);
+            HIPCHK(c, lbm::launch_step(c->p.prec, lbm::MODE_CHECK, L, c->stream));
+            c->cur = 1 - c->cur;
+            c->steps_done++;
+            k++;
+            HIPCHK(c, lbm::launch_finalize(c->partials, nblocks(c), c->red_dev, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->red_host, c->red_dev, sizeof(double) * lbm::kPartialStride,
+                                     hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            int rc = evaluate_check(c);
+            if (rc) return rc;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx *c, double *rho1, double *rho2, double *uF, int on_device) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "lbm_moments: NULL context");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t NB = sizeof(double) * (size_t)c->N;
+    if (on_device) {
+        // solid sites are not written by the kernel: they report 0
+        if (rho1) HIPCHK(c, hipMemsetAsync(rho1, 0, NB, c->stream));
+        if (rho2) HIPCHK(c, hipMemsetAsync(rho2, 0, NB, c->stream));
+        if (uF) HIPCHK(c, hipMemsetAsync(uF, 0, 3 * NB, c->stream));
+        return measure(c, rho1, rho2, uF);
+    }
+    int rc = ensure_stage(c);
+    if (rc) return rc;
+    double *d0 = rho1 ? c->stage : nullptr, *d1 = rho2 ? c->stage + c->N : nullptr;
+    double *du = uF ? c->stage + 2 * c->N : nullptr;
+    if (d0) HIPCHK(c, hipMemsetAsync(d0, 0, NB, c->stream));
+    if (d1) HIPCHK(c, hipMemsetAsync(d1, 0, NB, c->stream));
+    if (du) HIPCHK(c, hipMemsetAsync(du, 0, 3 * NB, c->stream));
+    rc = measure(c, d0, d1, du);
+    if (rc) return rc;
+    if (rho1) HIPCHK(c, hipMemcpy(rho1, d0, NB, hipMemcpyDeviceToHost));
+    if (rho2) HIPCHK(c, hipMemcpy(rho2, d1, NB, hipMemcpyDeviceToHost));
+    if (uF) HIPCHK(c, hipMemcpy(uF, du, 3 * NB, hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+
+int lbm_reduce(lbm_ctx *c, double out[5]) {
+    if (!c || !out) return fail(c, LBM_EINVAL, "lbm_reduce: NULL argument");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = measure(c, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    for (int k = 0; k < 5; ++k) out[k] = c->red_host[k];
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_ctx *c, double *f, int on_device) {
+    if (!c || !f) return fail(c, LBM_EINVAL, "lbm_get_populations: NULL argument");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t bytes = sizeof(double) * 38 * (size_t)c->N;
+    double *dst = f;
+    if (!on_device && hipMalloc(&dst, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, LBM_ENOMEM, "cannot allocate the population staging buffer");
+    }
+    hipError_t e = lbm::launch_get_pops(c->p.prec, c->f[c->cur], c->links, dst, c->p.nx, c->p.ny, c->p.nz, c->plane,
+                                        c->ref, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && !on_device) e = hipMemcpy(f, dst, bytes, hipMemcpyDeviceToHost);
+    if (!on_device) (void)hipFree(dst);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("get_populations: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx *c, const double *f, int on_device) {
+    if (!c || !f) return fail(c, LBM_EINVAL, "lbm_set_populations: NULL argument");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t bytes = sizeof(double) * 38 * (size_t)c->N;
+    double *src = const_cast<double *>(f);
+    if (!on_device) {
+        if (hipMalloc(&src, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, LBM_ENOMEM, "cannot allocate the population staging buffer");
+        }
+        if (hipMemcpy(src, f, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(src);
+            return fail(c, LBM_EDEVICE, "set_populations: copy failed");
+        }
+    }
+    hipError_t e = lbm::launch_set_pops(c->p.prec, c->f[c->cur], c->links, src, c->p.nx, c->p.ny, c->p.nz, c->plane,
+                                        c->ref, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (!on_device) (void)hipFree(src);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("set_populations: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_set_fields(lbm_ctx *c, const double *rho1, const double *rho2, const double *u, int on_device) {
+    if (!c || !rho1 || !rho2) return fail(c, LBM_EINVAL, "lbm_set_fields: NULL argument");
+    HIPCHK(c, hipSetDevice(c->device));
+    return load_fields(c, rho1, rho2, u, on_device);
+}
+
+int lbm_info(const lbm_ctx *c, lbm_info_t *out) {
+    if (!c || !out) return LBM_EINVAL;
+    out->n_sites = c->N;
+    out->n_fluid = c->nfluid;
+    out->steps_done = c->steps_done;
+    out->bytes_per_lu = (int32_t)(2 * 2 * 19 * c->esz);
+    out->tile_x = c->tile_x;
+    out->tile_y = c->tile_y;
+    out->zchunk = c->zchunk;
+    out->blocks = nblocks(c);
+    out->mass0[0] = c->mass0[0];
+    out->mass0[1] = c->mass0[1];
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+void lbm_free(lbm_ctx *c) { release(c); }
+
+// ---------------------------------------------------------------------------
+// Batches of contexts stepped by one launch per step.
+// ---------------------------------------------------------------------------
+
+int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, lbm_batch **out) {
+    if (!out) return bfail(nullptr, LBM_EINVAL, "lbm_batch_create: out is NULL");
+    *out = nullptr;
+    if (!ctxs || n < 1) return bfail(nullptr, LBM_EINVAL, "lbm_batch_create: no contexts");
+    for (int d = 0; d < n; ++d) {
+        if (!ctxs[d]) return bfail(nullptr, LBM_EINVAL, "lbm_batch_create: NULL context");
+        if (ctxs[d]->p.prec != ctxs[0]->p.prec || ctxs[d]->tile_x != ctxs[0]->tile_x ||
+            ctxs[d]->tile_y != ctxs[0]->tile_y || ctxs[d]->device != ctxs[0]->device)
+            return bfail(nullptr, LBM_EINVAL, "lbm_batch_create: contexts differ in precision, tile or device");
+        for (int e = 0; e < d; ++e)
+            if (ctxs[e] == ctxs[d]) return bfail(nullptr, LBM_EINVAL, "lbm_batch_create: a context appears twice");
+    }
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return bfail(nullptr, LBM_ENOMEM, "cannot allocate the batch");
+    b->ctx.assign(ctxs, ctxs + n);
+    b->prec = ctxs[0]->p.prec;
+    b->tile_x = ctxs[0]->tile_x;
+    b->tile_y = ctxs[0]->tile_y;
+    b->desc_size = lbm::batch_desc_size(b->prec);
+    b->descs_host.resize(b->desc_size * n);
+    // Work list: every tile of every domain, domain by domain, the largest
+    // domains first so that their long columns of work start early.
+    std::vector<int> order(n);
+    for (int d = 0; d < n; ++d) order[d] = d;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nblocks(ctxs[x]) > nblocks(ctxs[y]); });
+    std::vector<int2> work;
+    for (int d : order)
+        for (int k = 0; k < nblocks(ctxs[d]); ++k) work.push_back(make_int2(d, k));
+    b->nwork = (int)work.size();
+    auto bail = [&](int rc) {
+        g_init_error = b->err;
+        lbm_batch_free(b);
+        return rc;
+    };
+    if (hipSetDevice(ctxs[0]->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(bfail(b, LBM_EDEVICE, "cannot create the batch stream"));
+    if (hipMalloc(&b->descs_dev, b->descs_host.size()) != hipSuccess ||
+        hipMalloc(&b->work_dev, sizeof(int2) * work.size()) != hipSuccess)
+        return bail(bfail(b, LBM_ENOMEM, "cannot allocate the batch tables"));
+    if (hipMemcpy(b->work_dev, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(bfail(b, LBM_EDEVICE, "cannot upload the work list"));
+    *out = b;
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Descriptors from each context's current buffers (an even step reads f[cur]).
+int upload_descs(lbm_batch *b) {
+    for (size_t d = 0; d < b->ctx.size(); ++d) {
+        lbm_ctx *c = b->ctx[d];
+        lbm::StepLaunch L = make_launch(c, c->f[c->cur], c->f[1 - c->cur]);
+        lbm::fill_batch_desc(b->prec, L, b->descs_host.data() + d * b->desc_size);
+    }
+    if (hipMemcpyAsync(b->descs_dev, b->descs_host.data(), b->descs_host.size(), hipMemcpyHostToDevice, b->stream) !=
+        hipSuccess)
+        return bfail(b, LBM_EDEVICE, "cannot upload the batch descriptors");
+    return LBM_OK;
+}
+
+bool capture_batch_graph(lbm_batch *b) {
+    if (b->graphs_off) return false;
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        b->graphs_off = true;
+        return false;
+    }
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < kGraphSteps && e == hipSuccess; ++j)
+        e = lbm::launch_batch(b->prec, lbm::MODE_STEP, b->tile_x, b->tile_y, b->descs_dev, b->work_dev, b->nwork,
+                              j & 1, b->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g || hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        b->gexec = nullptr;
+        b->graphs_off = true;
+        return false;
+    }
+    b->graph = g;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_step(lbm_batch *b, int64_t n) {
+    if (!b) return bfail(nullptr, LBM_EINVAL, "lbm_batch_step: NULL batch");
+    if (n < 0) return bfail(b, LBM_EINVAL, "lbm_batch_step: n < 0");
+    if (hipSetDevice(b->ctx[0]->device) != hipSuccess) return bfail(b, LBM_EDEVICE, "hipSetDevice failed");
+    for (lbm_ctx *c : b->ctx)
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return bfail(b, LBM_EDEVICE, "context stream failed");
+    int rc = upload_descs(b);
+    if (rc) return rc;
+    int flip = 0;   // parity of the steps done since the descriptors were built
+    auto advance = [&](int64_t m) {
+        for (lbm_ctx *c : b->ctx) {
+            c->steps_done += m;
+            if (m & 1) c->cur = 1 - c->cur;
+        }
+    };
+    int64_t k = 0;
+    while (k < n) {
+        int64_t plain = n - k;
+        for (lbm_ctx *c : b->ctx) plain = std::min(plain, plain_steps_before_check(c->steps_done, c->p.check_every));
+        if (plain >= kGraphSteps + flip) {
+            if (flip) {  // align to an even step before replaying
+                if (lbm::launch_batch(b->prec, lbm::MODE_STEP, b->tile_x, b->tile_y, b->descs_dev, b->work_dev,
+                                      b->nwork, 1, b->stream) != hipSuccess)
+                    return bfail(b, LBM_EDEVICE, "batch launch failed");
+                advance(1);
+                flip = 0;
+                ++k;
+                --plain;
+            }
+            while (plain >= kGraphSteps && (b->gexec || capture_batch_graph(b))) {
+                if (hipGraphLaunch(b->gexec, b->stream) != hipSuccess) return bfail(b, LBM_EDEVICE, "graph launch failed");
+                advance(kGraphSteps);
+                k += kGraphSteps;
+                plain -= kGraphSteps;
+            }
+        }
+        for (; plain > 0; --plain, ++k) {
+            if (lbm::launch_batch(b->prec, lbm::MODE_STEP, b->tile_x, b->tile_y, b->descs_dev, b->work_dev, b->nwork,
+                                  flip, b->stream) != hipSuccess)
+                return bfail(b, LBM_EDEVICE, "batch launch failed");
+            advance(1);
+            flip ^= 1;
+        }
+        if (k < n) {  // a check step for at least one domain
+            if (lbm::launch_batch(b->prec, lbm::MODE_CHECK, b->tile_x, b->tile_y, b->descs_dev, b->work_dev, b->nwork,
+                                  flip, b->stream) != hipSuccess)
+                return bfail(b, LBM_EDEVICE, "batch launch failed");
+            std::vector<lbm_ctx *> due;
+            for (lbm_ctx *c : b->ctx)
+                if (c->p.check_every > 0 && (c->steps_done + 1) % c->p.check_every == 0) due.push_back(c);
+            advance(1);
+            flip ^= 1;
+            ++k;
+            for (lbm_ctx *c : due) {
+                if (lbm::launch_finalize(c->partials, nblocks(c), c->red_dev, b->stream) != hipSuccess ||
+                    hipMemcpyAsync(c->red_host, c->red_dev, sizeof(double) * lbm::kPartialStride,
+                                   hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+                    return bfail(b, LBM_EDEVICE, "batch check failed");
+            }
+            if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, LBM_EDEVICE, "batch stream failed");
+            for (size_t d = 0; d < b->ctx.size(); ++d) {
+                lbm_ctx *c = b->ctx[d];
+                if (std::find(due.begin(), due.end(), c) == due.end()) continue;
+                int r = evaluate_check(c);
+                if (r) return bfail(b, r, "domain " + std::to_string(d) + ": " + c->err);
+            }
+        }
+    }
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, LBM_EDEVICE, "batch stream failed");
+    return LBM_OK;
+}
+
+const char *lbm_batch_last_error(const lbm_batch *b) { return b ? b->err.c_str() : g_init_error.c_str(); }
+
+void lbm_batch_free(lbm_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->descs_dev) (void)hipFree(b->descs_dev);
+    if (b->work_dev) (void)hipFree(b->work_dev);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// lbm_internal.h -- declarations shared by the kernels (lbm_kernels.hip) and
+// the C ABI implementation (lbm_api.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/lbm.h"
+
+namespace lbm {
+
+// Kernel flavours of the fused step (one source, selected at compile time).
+enum Mode : int {
+    MODE_STEP = 0,     // advance: write post-collision populations
+    MODE_CHECK = 1,    // advance and accumulate FP64 block sums for the check
+    MODE_MOMENTS = 2,  // no advance: write rho_1, rho_2, u_F of the current state
+    MODE_REDUCE = 3,   // no advance: FP64 block sums only
+};
+
+// Per-block partial sums written by MODE_CHECK / MODE_REDUCE:
+// [rho1, rho2, rho uF_x, rho uF_y, rho uF_z, non-finite count, 0, 0].
+constexpr int kPartialStride = 8;
+
+// Everything a step launch needs, by value.  Physical parameters are kept
+// in double; each kernel converts them to its compute type.
+struct StepLaunch {
+    const void *src;
+    void *dst;
+    const uint32_t *links;
+    int nx, ny, nz;
+    int64_t plane;          // elements per (component, direction) plane
+    int tile_x, tile_y, zchunk;
+    int ntx, nty, nzc;      // tiles in x, y and chunks in z
+    double tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
+    int eq_kind, force_kind;
+    double *partials;       // kPartialStride doubles per block
+    double *out_rho0, *out_rho1, *out_u;  // MODE_MOMENTS outputs (N, N, 3N)
+};
+
+// Launches one fused step (or moments / reduce pass) of precision prec.
+hipError_t launch_step(int prec, Mode mode, const StepLaunch &L, hipStream_t s);
+// Sums nblocks partials (fixed order) into out[kPartialStride] on the device.
+hipError_t launch_finalize(const double *partials, int nblocks, double *out, hipStream_t s);
+// Per-site link mask: bit 0 = site solid, bit i = site - c_i solid (periodic).
+hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, int nz, hipStream_t s);
+// Internal state from fields: f*_j(x) = f_eq,j(x + c_j) if that site is fluid,
+// else f_eq,opp(j)(x); f_eq from rho (2N), u (3N or null).
+hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const double *rho0,
+                              const double *rho1, const double *u, int nx, int ny, int nz,
+                              int64_t plane, int eq_kind, const double ref[2], hipStream_t s);
+// Internal state from ABI populations (inverse of the pull).
+hipError_t launch_set_pops(int prec, void *dst, const uint32_t *links, const double *f, int nx,
+                           int ny, int nz, int64_t plane, const double ref[2], hipStream_t s);
+// ABI populations from the internal state (the pull).
+hipError_t launch_get_pops(int prec, const void *src, const uint32_t *links, double *f, int nx,
+                           int ny, int nz, int64_t plane, const double ref[2], hipStream_t s);
+
+// Batched launches over many domains: a descriptor per domain (the typed
+// kernel arguments, built by fill_batch_desc from a StepLaunch) and a work list
+// of (domain, tile) pairs; flip swaps each descriptor's (src, dst).
+size_t batch_desc_size(int prec);
+void fill_batch_desc(int prec, const StepLaunch &L, void *out);
+hipError_t launch_batch(int prec, Mode mode, int tx, int ty, const void *descs, const int2 *work, int nwork,
+                        int flip, hipStream_t s);
+
+// Tile shapes the step kernel is compiled for.
+bool tile_supported(int tx, int ty);
+
+}  // namespace lbm

@@ -1,0 +1,828 @@
+// lbm_kernels.hip -- gfx950 kernels of the two-component Shan-Chen D3Q19 step
+// (Otomo et al., arXiv:1711.03254, Section 2, Eqs. 1-11).
+//
+// Storage: per (component, direction) plane a contiguous array of N sites,
+// x fastest.  The buffer a step reads holds the post-collision populations
+// f*(x, t-1) of the previous step; the step pulls f_i(x, t) = f*_i(x - c_i)
+// (or, when x - c_i is solid, the reversed population f*_opp(i)(x): halfway
+// bounce-back), collides and writes f*(x, t) at x into the other buffer.
+//
+// The Shan-Chen force at x needs the densities of the 18 neighbours at time
+// t, which exist only after those neighbours have pulled.  A block owns an
+// x-y tile of TX x TY columns and marches along z through a chunk of planes;
+// for every plane it pulls the tile and its one-site ring, sums the
+// densities into an LDS ring buffer of four planes, and collides the plane
+// behind once the plane ahead is known.  The ring's pulls are the only
+// redundant work (loads that mostly hit L2); no density array goes to HBM.
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+// ---------------------------------------------------------------------------
+// D3Q19 in the ABI order (rest; +x -x +y -y +z -z; xy, xz, yz diagonals).
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int cx_of(int i) {
+    return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
+           : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
+}
+__host__ __device__ constexpr int cy_of(int i) {
+    return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
+           : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int cz_of(int i) {
+    return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
+           : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
+}
+__host__ __device__ constexpr int opp_of(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr double w_of(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+// Compile-time loop: f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>).
+template <int... Is, class F>
+__device__ __forceinline__ void sfor_impl(std::integer_sequence<int, Is...>, F &&f) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void sfor(F &&f) {
+    sfor_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+// ---------------------------------------------------------------------------
+// Storage codecs.  16-bit formats hold the deviation f_i - w_i rho_ref[a].
+// ---------------------------------------------------------------------------
+template <typename S> struct Codec;
+template <> struct Codec<double> {
+    using C = double;
+    static constexpr bool shifted = false;
+    __device__ static double ld(double v) { return v; }
+    __device__ static double st(double v) { return v; }
+};
+template <> struct Codec<float> {
+    using C = float;
+    static constexpr bool shifted = false;
+    __device__ static float ld(float v) { return v; }
+    __device__ static float st(float v) { return v; }
+};
+template <> struct Codec<__half> {
+    using C = float;
+    static constexpr bool shifted = true;
+    __device__ static float ld(__half v) { return __half2float(v); }
+    __device__ static __half st(float v) { return __float2half_rn(v); }
+};
+template <> struct Codec<__hip_bfloat16> {
+    using C = float;
+    static constexpr bool shifted = true;
+    __device__ static float ld(__hip_bfloat16 v) { return __bfloat162float(v); }
+    __device__ static __hip_bfloat16 st(float v) { return __float2bfloat16(v); }
+};
+
+template <typename S>
+struct KArgs {
+    using C = typename Codec<S>::C;
+    const S *src;
+    S *dst;
+    const uint32_t *links;
+    int nx, ny, nz, ntx, nty, zchunk;
+    uint32_t plane_bytes;   // bytes of one (component, direction) plane
+    C tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
+    int eq_kind, force_kind;
+    double *partials;
+    double *out_rho0, *out_rho1, *out_u;
+    int64_t n_sites;
+};
+
+__device__ __forceinline__ int wrap(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Byte offsets of the source sites (x - cx, y - cy) for cx, cy in {-1,0,1},
+// index (cy + 1) * 3 + (cx + 1), of one column.
+struct Column {
+    uint32_t xy[9];
+    uint32_t site;   // x + nx y (element index)
+};
+
+__device__ __forceinline__ Column make_column(int x, int y, int nx, int ny, uint32_t esz) {
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    const int sx[3] = {xp, x, xm};           // source x of cx = -1, 0, +1
+    const int sy[3] = {yp * nx, y * nx, ym * nx};
+    Column c;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) c.xy[j * 3 + k] = (uint32_t)(sx[k] + sy[j]) * esz;
+    c.site = (uint32_t)(x + y * nx);
+    return c;
+}
+
+// Byte offsets of the source planes z - cz for cz = -1, 0, +1.
+__device__ __forceinline__ void plane_offsets(int z, int nz, uint32_t nxy_bytes, uint32_t (&sz)[3]) {
+    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+    sz[0] = (uint32_t)zp * nxy_bytes;
+    sz[1] = (uint32_t)z * nxy_bytes;
+    sz[2] = (uint32_t)zm * nxy_bytes;
+}
+
+// Pull of one fluid site: f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) when the
+// link bit i says x - c_i is solid.  The two members of an opposite pair
+// (odd i, i + 1) are addressed from the odd member's plane, so a reversed
+// read is an offset of +- one plane and the choice is a select on a 32-bit
+// offset.  Only issues the 38 loads (raw storage values): a plane's interior
+// and ring loads are all in flight before any of them is consumed.
+template <typename S>
+__device__ __forceinline__ void issue_pull(const KArgs<S> &a, const Column &col, const uint32_t (&sz)[3], uint32_t L,
+                                           bool active, S (&raw)[2][19]) {
+    const char *base = reinterpret_cast<const char *>(a.src);
+    const uint32_t pb = a.plane_bytes;
+    const uint32_t self = col.xy[4] + sz[1];
+    // An inactive lane (a solid site, or no ring site) reads the first element
+    // of each plane instead: always in bounds, a cache hit after the first
+    // lane, and the issue stays free of branches.
+    const uint32_t on = active ? 0xffffffffu : 0u;
+    sfor<19>([&](auto I) {
+        constexpr int i = I;
+        uint32_t off;
+        const char *p;
+        if constexpr (i == 0) {
+            off = self;
+            p = base;
+        } else {
+            constexpr int lo = (i & 1) ? i : i - 1;   // odd member of the pair
+            const uint32_t stream = col.xy[(cy_of(i) + 1) * 3 + cx_of(i) + 1] + sz[cz_of(i) + 1];
+            const bool wall = (L >> i) & 1u;
+            if constexpr (i == lo) off = wall ? self + pb : stream;
+            else off = wall ? self : stream + pb;
+            p = base + (size_t)lo * pb;
+        }
+        off &= on;
+        raw[0][i] = *reinterpret_cast<const S *>(p + off);
+        raw[1][i] = *reinterpret_cast<const S *>(p + (size_t)19 * pb + off);
+    });
+}
+
+template <typename S>
+__device__ __forceinline__ typename Codec<S>::C decode(S v, int i, typename Codec<S>::C ref) {
+    using C = typename Codec<S>::C;
+    C x = Codec<S>::ld(v);
+    if constexpr (Codec<S>::shifted) x += C(w_of(i)) * ref;
+    return x;
+}
+
+// Eq. (4) and the second moments of one component's pulled populations:
+// everything the regularized collision needs from them.
+template <typename C>
+struct Moments {
+    C r, jx, jy, jz, xx, yy, zz, xy, xz, yz;
+};
+
+template <typename S>
+__device__ __forceinline__ Moments<typename Codec<S>::C> moments_of(const S (&raw)[19], typename Codec<S>::C ref) {
+    using C = typename Codec<S>::C;
+    Moments<C> m{C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
+    sfor<19>([&](auto I) {
+        constexpr int i = I;
+        constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+        const C v = decode<S>(raw[i], i, ref);
+        m.r += v;
+        if constexpr (X > 0) { m.jx += v; m.xx += v; }
+        if constexpr (X < 0) { m.jx -= v; m.xx += v; }
+        if constexpr (Y > 0) { m.jy += v; m.yy += v; }
+        if constexpr (Y < 0) { m.jy -= v; m.yy += v; }
+        if constexpr (Z > 0) { m.jz += v; m.zz += v; }
+        if constexpr (Z < 0) { m.jz -= v; m.zz += v; }
+        if constexpr (X * Y > 0) m.xy += v;
+        if constexpr (X * Y < 0) m.xy -= v;
+        if constexpr (X * Z > 0) m.xz += v;
+        if constexpr (X * Z < 0) m.xz -= v;
+        if constexpr (Y * Z > 0) m.yz += v;
+        if constexpr (Y * Z < 0) m.yz -= v;
+    });
+    return m;
+}
+
+template <typename S>
+__device__ __forceinline__ typename Codec<S>::C density_of(const S (&raw)[19], typename Codec<S>::C ref) {
+    using C = typename Codec<S>::C;
+    C r = C(0);
+    sfor<19>([&](auto I) {
+        constexpr int i = I;
+        r += decode<S>(raw[i], i, ref);
+    });
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// The fused step.
+// ---------------------------------------------------------------------------
+// Consecutive block ids are dispatched to different XCDs in turn; remap so
+// that each XCD receives a contiguous range of work items (neighbouring tiles
+// then share its L2).
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+    const int per = nblocks >> 3;
+    return b < (per << 3) ? (b & 7) * per + (b >> 3) : b;
+}
+
+// One block's work: the tile with linear index b = tx + ntx (ty + nty zc) of
+// the domain described by a; partial sums (MODE_CHECK / MODE_MOMENTS) go to
+// a.partials[slot].
+//
+// Per plane: the tile's and the ring's pulls are issued together; the
+// interior keeps only the ten moments per component of its site (the
+// regularized collision rebuilds f* from them and the force), the ring only
+// its densities.  The collision of a plane waits for the next plane's
+// densities (one barrier per plane).
+template <typename S, int TX, int TY, int MODE>
+__device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
+    using C = typename Codec<S>::C;
+    constexpr int NT = TX * TY;
+    constexpr int RW = TX + 2, RH = TY + 2;
+    constexpr int NR = 2 * RW + 2 * TY;       // ring sites of the tile
+    static_assert(NR <= NT, "the ring must fit in the block");
+    constexpr uint32_t ESZ = sizeof(S);
+    constexpr C T0 = C(1.0 / 3.0);
+
+    __shared__ C psi0[4][RH][RW];
+    __shared__ C psi1[4][RH][RW];
+    __shared__ double red[NT / 64][6];
+
+    const int tx = b % a.ntx;
+    b /= a.ntx;
+    const int ty = b % a.nty;
+    const int zc = b / a.nty;
+    const int z0 = zc * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.nz);
+
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int gx = tx * TX + lx, gy = ty * TY + ly;
+    const bool inside = gx < a.nx && gy < a.ny;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t nxyB = nxy * ESZ;
+
+    // This thread's ring site, in LDS coordinates (rr, rc).
+    int rr, rc;
+    if (tid < RW) { rr = 0; rc = tid; }
+    else if (tid < 2 * RW) { rr = RH - 1; rc = tid - RW; }
+    else if (tid < 2 * RW + TY) { rr = 1 + tid - 2 * RW; rc = 0; }
+    else { rr = 1 + tid - 2 * RW - TY; rc = RW - 1; }
+    const bool has_ring = tid < NR;
+    const bool ring_wave = (tid & ~63) < NR;   // the wave holds at least one ring site
+
+    const Column ci = make_column(gx % nx, gy % ny, nx, ny, ESZ);
+    const Column cr = make_column(wrap(tx * TX - 1 + rc, nx), wrap(ty * TY - 1 + rr, ny), nx, ny, ESZ);
+
+    Moments<C> mc[2], mn[2];     // moments of the plane to collide / of the next plane
+    bool fluid_c = false, fluid_n = false;
+    const C ref0 = a.ref0, ref1 = a.ref1;
+
+    // link words, fetched one plane ahead
+    auto zwrap = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+    uint32_t Li = a.links[ci.site + (uint32_t)zwrap(z0 - 1) * nxy];
+    uint32_t Lr = has_ring ? a.links[cr.site + (uint32_t)zwrap(z0 - 1) * nxy] : 1u;
+
+    // Pulls plane zw into LDS slot `slot`; the interior's moments go to mn.
+    auto load_plane = [&](int zw, int lslot, bool keep, int zw_next) {
+        uint32_t sz[3];
+        plane_offsets(zw, nz, nxyB, sz);
+        const uint32_t Lin = a.links[ci.site + (uint32_t)zw_next * nxy];
+        const uint32_t Lrn = has_ring ? a.links[cr.site + (uint32_t)zw_next * nxy] : 1u;
+        const bool fi = !(Li & 1u), fr = !(Lr & 1u);
+        S ri[2][19], rg[2][19];
+        // All of the plane's loads are issued before any is consumed: one
+        // memory round trip per plane.  Waves without ring sites skip the
+        // ring issue (a uniform branch).
+        issue_pull<S>(a, ci, sz, Li, fi, ri);
+        if (ring_wave) issue_pull<S>(a, cr, sz, Lr, fr, rg);
+        __builtin_amdgcn_sched_barrier(0);
+        C r0, r1;
+        if (keep) {
+            mn[0] = moments_of<S>(ri[0], ref0);
+            mn[1] = moments_of<S>(ri[1], ref1);
+            r0 = mn[0].r;
+            r1 = mn[1].r;
+        } else {
+            r0 = density_of<S>(ri[0], ref0);
+            r1 = density_of<S>(ri[1], ref1);
+        }
+        if (!fi) {
+            r0 = a.wall0;
+            r1 = a.wall1;
+        }
+        fluid_n = fi;
+        psi0[lslot][ly + 1][lx + 1] = r0;
+        psi1[lslot][ly + 1][lx + 1] = r1;
+        if (ring_wave) {
+            C q0 = density_of<S>(rg[0], ref0), q1 = density_of<S>(rg[1], ref1);
+            if (!fr) {
+                q0 = a.wall0;
+                q1 = a.wall1;
+            }
+            if (has_ring) {
+                psi0[lslot][rr][rc] = q0;
+                psi1[lslot][rr][rc] = q1;
+            }
+        }
+        Li = Lin;
+        Lr = Lrn;
+    };
+
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+
+    load_plane(zwrap(z0 - 1), 0, false, z0);
+    load_plane(z0, 1, true, zwrap(z0 + 1));
+    mc[0] = mn[0];
+    mc[1] = mn[1];
+    fluid_c = fluid_n;
+
+    for (int z = z0; z < z1; ++z) {
+        const int sm = (z - z0) & 3, s0 = (z - z0 + 1) & 3, sp = (z - z0 + 2) & 3;
+        load_plane(zwrap(z + 1), sp, true, zwrap(z + 2));
+        __syncthreads();
+
+        if (inside && fluid_c) {
+            const C rho[2] = {mc[0].r, mc[1].r};
+
+            // Eqs. (7), (11): sum_i w_i c_i psi'(x + c_i) from the LDS planes.
+            C n0x = 0, n0y = 0, n0z = 0, n1x = 0, n1y = 0, n1z = 0;
+            sfor<19>([&](auto I) {
+                constexpr int i = I;
+                if constexpr (i > 0) {
+                    constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+                    constexpr C w = C(w_of(i));
+                    const int sl = Z == 0 ? s0 : (Z > 0 ? sp : sm);
+                    const C p0 = psi0[sl][ly + 1 + Y][lx + 1 + X];
+                    const C p1 = psi1[sl][ly + 1 + Y][lx + 1 + X];
+                    if constexpr (X != 0) { n0x += C(X) * w * p0; n1x += C(X) * w * p1; }
+                    if constexpr (Y != 0) { n0y += C(Y) * w * p0; n1y += C(Y) * w * p1; }
+                    if constexpr (Z != 0) { n0z += C(Z) * w * p0; n1z += C(Z) * w * p1; }
+                }
+            });
+            // Force on component 0 from component 1 and vice versa, plus body force.
+            C Fx[2], Fy[2], Fz[2];
+            Fx[0] = a.G * rho[0] * n1x + rho[0] * a.gx;
+            Fy[0] = a.G * rho[0] * n1y + rho[0] * a.gy;
+            Fz[0] = a.G * rho[0] * n1z + rho[0] * a.gz;
+            Fx[1] = a.G * rho[1] * n0x + rho[1] * a.gx;
+            Fy[1] = a.G * rho[1] * n0y + rho[1] * a.gy;
+            Fz[1] = a.G * rho[1] * n0z + rho[1] * a.gz;
+
+            // Eq. (8): u_F = (j_1 + j_2 + F / 2) / rho.
+            const C rho_t = rho[0] + rho[1];
+            const C inv = C(1) / rho_t;
+            const C ux = (mc[0].jx + mc[1].jx + C(0.5) * (Fx[0] + Fx[1])) * inv;
+            const C uy = (mc[0].jy + mc[1].jy + C(0.5) * (Fy[0] + Fy[1])) * inv;
+            const C uz = (mc[0].jz + mc[1].jz + C(0.5) * (Fz[0] + Fz[1])) * inv;
+            const C usq = ux * ux + uy * uy + uz * uz;
+
+            if constexpr (MODE == MODE_CHECK || MODE == MODE_MOMENTS) {
+                const bool ok = isfinite(rho[0]) && isfinite(rho[1]) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+                acc[0] += (double)rho[0];
+                acc[1] += (double)rho[1];
+                acc[2] += (double)rho_t * (double)ux;
+                acc[3] += (double)rho_t * (double)uy;
+                acc[4] += (double)rho_t * (double)uz;
+                acc[5] += ok ? 0.0 : 1.0;
+            }
+            if constexpr (MODE == MODE_MOMENTS) {
+                const uint32_t s = ci.site + (uint32_t)z * nxy;
+                if (a.out_rho0) a.out_rho0[s] = (double)rho[0];
+                if (a.out_rho1) a.out_rho1[s] = (double)rho[1];
+                if (a.out_u) {
+                    a.out_u[s] = (double)ux;
+                    a.out_u[(size_t)a.n_sites + s] = (double)uy;
+                    a.out_u[2 * (size_t)a.n_sites + s] = (double)uz;
+                }
+            }
+
+            if constexpr (MODE == MODE_STEP || MODE == MODE_CHECK) {
+                // Eqs. (5)-(6) with p = rho_1 / rho: tau_mix is linear in p.
+                const C tau = (rho[0] * a.tau0 + rho[1] * a.tau1) * inv;
+                const C omega = C(1) / tau;
+                const C keep = C(1) - omega;
+                const C guo = a.force_kind == 0 ? C(1) - C(0.5) * omega : C(0);
+                const C r2 = a.eq_kind == 1 ? C(1) : C(0);
+
+                // Per component: X = (1 - 1/tau) Pi_neq + guo (u_F F + F u_F),
+                // projected by Phi of Eq. (10) into 4.5 w_i (c_i c_i - T0 I) : X.
+                C Xxx[2], Xyy[2], Xzz[2], Xxy[2], Xxz[2], Xyz[2], trX[2];
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    const C rt = rho[d] * T0;
+                    const C ru = r2 * rho[d];
+                    Xxx[d] = keep * (mc[d].xx - rt - ru * ux * ux) + guo * C(2) * ux * Fx[d];
+                    Xyy[d] = keep * (mc[d].yy - rt - ru * uy * uy) + guo * C(2) * uy * Fy[d];
+                    Xzz[d] = keep * (mc[d].zz - rt - ru * uz * uz) + guo * C(2) * uz * Fz[d];
+                    Xxy[d] = keep * (mc[d].xy - ru * ux * uy) + guo * (ux * Fy[d] + Fx[d] * uy);
+                    Xxz[d] = keep * (mc[d].xz - ru * ux * uz) + guo * (ux * Fz[d] + Fx[d] * uz);
+                    Xyz[d] = keep * (mc[d].yz - ru * uy * uz) + guo * (uy * Fz[d] + Fy[d] * uz);
+                    trX[d] = Xxx[d] + Xyy[d] + Xzz[d];
+                }
+
+                // Eqs. (3), (9): f* = w_i [rho P_i + 4.5 (cc:X - T0 tr X) + 1.5 c.F],
+                // P_i = 1 + 3 cu + 4.5 cu^3 - 4.5 cu u^2 (+ 4.5 cu^2 - 1.5 u^2 with eq_kind 1);
+                // split into the parts even and odd under c -> -c.
+                char *dbase = reinterpret_cast<char *>(a.dst);
+                const uint32_t pb = a.plane_bytes;
+                const uint32_t sofs = ci.xy[4] + (uint32_t)z * nxyB;
+                auto put = [&](int d, int i, C v) {
+                    if constexpr (Codec<S>::shifted) v -= C(w_of(i)) * (d == 0 ? ref0 : ref1);
+                    *reinterpret_cast<S *>(dbase + (size_t)(d * 19 + i) * pb + sofs) = Codec<S>::st(v);
+                };
+#pragma unroll
+                for (int d = 0; d < 2; ++d)
+                    put(d, 0, C(1.0 / 3.0) * (rho[d] * (C(1) - r2 * C(1.5) * usq) - C(1.5) * trX[d]));
+                sfor<19>([&](auto I) {
+                    constexpr int i = I;
+                    if constexpr (i > 0 && (i & 1)) {
+                        constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+                        constexpr C w = C(w_of(i));
+                        const C cu = C(X) * ux + C(Y) * uy + C(Z) * uz;
+                        const C even_c = C(1) + r2 * (C(4.5) * cu * cu - C(1.5) * usq);
+                        const C odd_c = cu * (C(3) + C(4.5) * (cu * cu - usq));
+#pragma unroll
+                        for (int d = 0; d < 2; ++d) {
+                            const C ccX = C(X * X) * Xxx[d] + C(Y * Y) * Xyy[d] + C(Z * Z) * Xzz[d] +
+                                          C(2 * X * Y) * Xxy[d] + C(2 * X * Z) * Xxz[d] + C(2 * Y * Z) * Xyz[d];
+                            const C cF = C(X) * Fx[d] + C(Y) * Fy[d] + C(Z) * Fz[d];
+                            const C E = rho[d] * even_c + C(4.5) * (ccX - T0 * trX[d]);
+                            const C O = rho[d] * odd_c + C(1.5) * cF;
+                            put(d, i, w * (E + O));
+                            put(d, i + 1, w * (E - O));
+                        }
+                    }
+                });
+            }
+        }
+
+        mc[0] = mn[0];
+        mc[1] = mn[1];
+        fluid_c = fluid_n;
+    }
+
+    if constexpr (MODE == MODE_CHECK || MODE == MODE_MOMENTS) {
+        const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double v = acc[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) red[wv][k] = v;
+        }
+        __syncthreads();
+        if (tid < 6) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NT / 64; ++q) s += red[q][tid];
+            a.partials[(size_t)slot * kPartialStride + tid] = s;
+        }
+    }
+}
+
+template <typename S, int TX, int TY, int MODE>
+__global__ void __launch_bounds__(TX *TY) step_kernel(KArgs<S> a) {
+    step_body<S, TX, TY, MODE>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
+}
+
+// Many domains in one launch: work item w = (domain, tile) of a list sorted
+// by domain; descs[d] describes domain d with (src, dst) of an even step,
+// swapped when flip is set.
+template <typename S, int TX, int TY, int MODE>
+__global__ void __launch_bounds__(TX *TY) batch_kernel(const KArgs<S> *descs, const int2 *work, int flip) {
+    const int2 w = work[xcd_remap(blockIdx.x, gridDim.x)];
+    KArgs<S> a = descs[w.x];
+    if (flip) {
+        const S *t = a.src;
+        a.src = a.dst;
+        a.dst = const_cast<S *>(t);
+    }
+    step_body<S, TX, TY, MODE>(a, w.y, w.y);
+}
+
+__global__ void finalize_kernel(const double *partials, int nblocks, double *out) {
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < kPartialStride; ++k) {
+        double s = 0.0;
+        for (int j = t; j < nblocks; j += 256) s += partials[(size_t)j * kPartialStride + k];
+        sh[t] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (t < w) sh[t] += sh[t + w];
+            __syncthreads();
+        }
+        if (t == 0) out[k] = sh[0];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up and exchange kernels (one thread per site).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void site_coords(int64_t s, int nx, int ny, int &x, int &y, int &z) {
+    x = (int)(s % nx);
+    const int64_t r = s / nx;
+    y = (int)(r % ny);
+    z = (int)(r / ny);
+}
+
+__device__ __forceinline__ int64_t site_shift(int x, int y, int z, int dx, int dy, int dz, int nx, int ny, int nz) {
+    x += dx; y += dy; z += dz;
+    x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+    y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    z = z < 0 ? z + nz : (z >= nz ? z - nz : z);
+    return x + (int64_t)nx * (y + (int64_t)ny * z);
+}
+
+__global__ void links_kernel(const uint8_t *solid, uint32_t *links, int nx, int ny, int nz) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        site_coords(s, nx, ny, x, y, z);
+        uint32_t L = (solid && solid[s]) ? 1u : 0u;
+        if (solid) {
+            sfor<19>([&](auto I) {
+                constexpr int i = I;
+                if constexpr (i > 0) {
+                    const int64_t src = site_shift(x, y, z, -cx_of(i), -cy_of(i), -cz_of(i), nx, ny, nz);
+                    if (solid[src]) L |= 1u << i;
+                }
+            });
+        }
+        links[s] = L;
+    }
+}
+
+// Equilibrium of Eq. (3) for direction i (double arithmetic).
+__device__ __forceinline__ double feq_dir(int i, double rho, double ux, double uy, double uz, int eq_kind) {
+    double w = 0, cu = 0;
+    sfor<19>([&](auto I) {
+        constexpr int j = I;
+        if (j == i) {
+            w = w_of(j);
+            cu = cx_of(j) * ux + cy_of(j) * uy + cz_of(j) * uz;
+        }
+    });
+    const double usq = ux * ux + uy * uy + uz * uz;
+    double br = 1.0 + 3.0 * cu + 4.5 * cu * cu * cu - 4.5 * cu * usq;
+    if (eq_kind == 1) br += 4.5 * cu * cu - 1.5 * usq;
+    return rho * w * br;
+}
+
+template <typename S>
+__device__ __forceinline__ void store_pop(S *dst, int64_t plane, int d, int i, int64_t s, double v, double ref) {
+    if constexpr (Codec<S>::shifted) v -= w_of(i) * ref;
+    dst[(int64_t)(d * 19 + i) * plane + s] = Codec<S>::st((typename Codec<S>::C)v);
+}
+
+template <typename S>
+__device__ __forceinline__ double load_pop(const S *src, int64_t plane, int d, int i, int64_t s, double ref) {
+    double v = (double)Codec<S>::ld(src[(int64_t)(d * 19 + i) * plane + s]);
+    if constexpr (Codec<S>::shifted) v += w_of(i) * ref;
+    return v;
+}
+
+template <typename S>
+__global__ void init_fields_kernel(S *dst, const uint32_t *links, const double *rho0, const double *rho1,
+                                   const double *u, int nx, int ny, int nz, int64_t plane, int eq_kind,
+                                   double ref0, double ref1) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t L = links[s];
+        if (L & 1u) continue;
+        int x, y, z;
+        site_coords(s, nx, ny, x, y, z);
+        sfor<19>([&](auto I) {
+            constexpr int j = I;
+            // f*_j(x) = f_j(x + c_j) if x + c_j is fluid, else f_opp(j)(x).
+            const bool wall = j != 0 && ((L >> opp_of(j)) & 1u);
+            const int64_t t = wall ? s : site_shift(x, y, z, cx_of(j), cy_of(j), cz_of(j), nx, ny, nz);
+            const int k = wall ? opp_of(j) : j;
+            const double ux = u ? u[t] : 0.0, uy = u ? u[N + t] : 0.0, uz = u ? u[2 * N + t] : 0.0;
+            store_pop<S>(dst, plane, 0, j, s, feq_dir(k, rho0[t], ux, uy, uz, eq_kind), ref0);
+            store_pop<S>(dst, plane, 1, j, s, feq_dir(k, rho1[t], ux, uy, uz, eq_kind), ref1);
+        });
+    }
+}
+
+template <typename S>
+__global__ void set_pops_kernel(S *dst, const uint32_t *links, const double *f, int nx, int ny, int nz,
+                                int64_t plane, double ref0, double ref1) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t L = links[s];
+        if (L & 1u) continue;
+        int x, y, z;
+        site_coords(s, nx, ny, x, y, z);
+        sfor<19>([&](auto I) {
+            constexpr int j = I;
+            const bool wall = j != 0 && ((L >> opp_of(j)) & 1u);
+            const int64_t t = wall ? s : site_shift(x, y, z, cx_of(j), cy_of(j), cz_of(j), nx, ny, nz);
+            const int k = wall ? opp_of(j) : j;
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+                store_pop<S>(dst, plane, d, j, s, f[(int64_t)(d * 19 + k) * N + t], d == 0 ? ref0 : ref1);
+        });
+    }
+}
+
+template <typename S>
+__global__ void get_pops_kernel(const S *src, const uint32_t *links, double *f, int nx, int ny, int nz,
+                                int64_t plane, double ref0, double ref1) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t L = links[s];
+        int x, y, z;
+        site_coords(s, nx, ny, x, y, z);
+        sfor<19>([&](auto I) {
+            constexpr int i = I;
+            // f_i(x) = f*_i(x - c_i) if x - c_i is fluid, else f*_opp(i)(x).
+            const bool wall = i != 0 && ((L >> i) & 1u);
+            const int64_t t = wall ? s : site_shift(x, y, z, -cx_of(i), -cy_of(i), -cz_of(i), nx, ny, nz);
+            const int k = wall ? opp_of(i) : i;
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+                f[(int64_t)(d * 19 + i) * N + s] =
+                    (L & 1u) ? 0.0 : load_pop<S>(src, plane, d, k, t, d == 0 ? ref0 : ref1);
+        });
+    }
+}
+
+inline int site_grid(int64_t N) {
+    const int64_t b = (N + 255) / 256;
+    return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+template <typename S>
+KArgs<S> make_kargs(const StepLaunch &L) {
+    using C = typename Codec<S>::C;
+    KArgs<S> a;
+    a.src = static_cast<const S *>(L.src);
+    a.dst = static_cast<S *>(L.dst);
+    a.links = L.links;
+    a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
+    a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk;
+    a.plane_bytes = (uint32_t)(L.plane * (int64_t)sizeof(S));
+    a.tau0 = (C)L.tau0; a.tau1 = (C)L.tau1; a.G = (C)L.G;
+    a.gx = (C)L.gx; a.gy = (C)L.gy; a.gz = (C)L.gz;
+    a.wall0 = (C)L.wall0; a.wall1 = (C)L.wall1; a.ref0 = (C)L.ref0; a.ref1 = (C)L.ref1;
+    a.eq_kind = L.eq_kind; a.force_kind = L.force_kind;
+    a.partials = L.partials;
+    a.out_rho0 = L.out_rho0; a.out_rho1 = L.out_rho1; a.out_u = L.out_u;
+    a.n_sites = (int64_t)L.nx * L.ny * L.nz;
+    return a;
+}
+
+template <typename S, int TX, int TY>
+hipError_t launch_typed(Mode mode, const StepLaunch &L, hipStream_t s) {
+    const KArgs<S> a = make_kargs<S>(L);
+    const dim3 grid((unsigned)(L.ntx * L.nty * L.nzc)), block(TX * TY);
+    switch (mode) {
+    case MODE_STEP: hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE_STEP>), grid, block, 0, s, a); break;
+    case MODE_CHECK: hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE_CHECK>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE_MOMENTS>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_tiles(Mode mode, const StepLaunch &L, hipStream_t s) {
+    if (L.tile_x == 64 && L.tile_y == 4) return launch_typed<S, 64, 4>(mode, L, s);
+    if (L.tile_x == 32 && L.tile_y == 8) return launch_typed<S, 32, 8>(mode, L, s);
+    if (L.tile_x == 16 && L.tile_y == 16) return launch_typed<S, 16, 16>(mode, L, s);
+    if (L.tile_x == 8 && L.tile_y == 32) return launch_typed<S, 8, 32>(mode, L, s);
+    if (L.tile_x == 64 && L.tile_y == 8) return launch_typed<S, 64, 8>(mode, L, s);
+    if (L.tile_x == 32 && L.tile_y == 16) return launch_typed<S, 32, 16>(mode, L, s);
+    return hipErrorInvalidValue;
+}
+
+template <typename S, int TX, int TY>
+hipError_t launch_batch_typed(Mode mode, const void *descs, const int2 *work, int nwork, int flip, hipStream_t s) {
+    const KArgs<S> *d = static_cast<const KArgs<S> *>(descs);
+    const dim3 grid((unsigned)nwork), block(TX * TY);
+    switch (mode) {
+    case MODE_STEP: hipLaunchKernelGGL((batch_kernel<S, TX, TY, MODE_STEP>), grid, block, 0, s, d, work, flip); break;
+    case MODE_CHECK: hipLaunchKernelGGL((batch_kernel<S, TX, TY, MODE_CHECK>), grid, block, 0, s, d, work, flip); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_batch_tiles(Mode mode, int tx, int ty, const void *descs, const int2 *work, int nwork, int flip,
+                              hipStream_t s) {
+    if (tx == 64 && ty == 4) return launch_batch_typed<S, 64, 4>(mode, descs, work, nwork, flip, s);
+    if (tx == 32 && ty == 8) return launch_batch_typed<S, 32, 8>(mode, descs, work, nwork, flip, s);
+    if (tx == 16 && ty == 16) return launch_batch_typed<S, 16, 16>(mode, descs, work, nwork, flip, s);
+    if (tx == 8 && ty == 32) return launch_batch_typed<S, 8, 32>(mode, descs, work, nwork, flip, s);
+    if (tx == 64 && ty == 8) return launch_batch_typed<S, 64, 8>(mode, descs, work, nwork, flip, s);
+    if (tx == 32 && ty == 16) return launch_batch_typed<S, 32, 16>(mode, descs, work, nwork, flip, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+size_t batch_desc_size(int prec) {
+    switch (prec) {
+    case LBM_FP64: return sizeof(KArgs<double>);
+    case LBM_FP32: return sizeof(KArgs<float>);
+    case LBM_FP16S: return sizeof(KArgs<__half>);
+    case LBM_BF16S: return sizeof(KArgs<__hip_bfloat16>);
+    default: return 0;
+    }
+}
+
+void fill_batch_desc(int prec, const StepLaunch &L, void *out) {
+    switch (prec) {
+    case LBM_FP64: *static_cast<KArgs<double> *>(out) = make_kargs<double>(L); break;
+    case LBM_FP32: *static_cast<KArgs<float> *>(out) = make_kargs<float>(L); break;
+    case LBM_FP16S: *static_cast<KArgs<__half> *>(out) = make_kargs<__half>(L); break;
+    case LBM_BF16S: *static_cast<KArgs<__hip_bfloat16> *>(out) = make_kargs<__hip_bfloat16>(L); break;
+    default: break;
+    }
+}
+
+hipError_t launch_batch(int prec, Mode mode, int tx, int ty, const void *descs, const int2 *work, int nwork, int flip,
+                        hipStream_t s) {
+    switch (prec) {
+    case LBM_FP64: return launch_batch_tiles<double>(mode, tx, ty, descs, work, nwork, flip, s);
+    case LBM_FP32: return launch_batch_tiles<float>(mode, tx, ty, descs, work, nwork, flip, s);
+    case LBM_FP16S: return launch_batch_tiles<__half>(mode, tx, ty, descs, work, nwork, flip, s);
+    case LBM_BF16S: return launch_batch_tiles<__hip_bfloat16>(mode, tx, ty, descs, work, nwork, flip, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool tile_supported(int tx, int ty) {
+    return (tx == 64 && ty == 4) || (tx == 32 && ty == 8) || (tx == 16 && ty == 16) || (tx == 8 && ty == 32) ||
+           (tx == 64 && ty == 8) || (tx == 32 && ty == 16);
+}
+
+hipError_t launch_step(int prec, Mode mode, const StepLaunch &L, hipStream_t s) {
+    switch (prec) {
+    case LBM_FP64: return launch_tiles<double>(mode, L, s);
+    case LBM_FP32: return launch_tiles<float>(mode, L, s);
+    case LBM_FP16S: return launch_tiles<__half>(mode, L, s);
+    case LBM_BF16S: return launch_tiles<__hip_bfloat16>(mode, L, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_finalize(const double *partials, int nblocks, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, int nz, hipStream_t s) {
+    hipLaunchKernelGGL(links_kernel, dim3(site_grid((int64_t)nx * ny * nz)), dim3(256), 0, s, solid, links, nx, ny, nz);
+    return hipGetLastError();
+}
+
+#define LBM_DISPATCH_PREC(prec, S, ...)                         \
+    switch (prec) {                                             \
+    case LBM_FP64: { using S = double; __VA_ARGS__; break; }    \
+    case LBM_FP32: { using S = float; __VA_ARGS__; break; }     \
+    case LBM_FP16S: { using S = __half; __VA_ARGS__; break; }   \
+    case LBM_BF16S: { using S = __hip_bfloat16; __VA_ARGS__; break; } \
+    default: return hipErrorInvalidValue;                       \
+    }
+
+hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const double *rho0, const double *rho1,
+                              const double *u, int nx, int ny, int nz, int64_t plane, int eq_kind, const double ref[2],
+                              hipStream_t s) {
+    const int g = site_grid((int64_t)nx * ny * nz);
+    LBM_DISPATCH_PREC(prec, S,
+                      hipLaunchKernelGGL(init_fields_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<S *>(dst), links,
+                                         rho0, rho1, u, nx, ny, nz, plane, eq_kind, ref[0], ref[1]));
+    return hipGetLastError();
+}
+
+hipError_t launch_set_pops(int prec, void *dst, const uint32_t *links, const double *f, int nx, int ny, int nz,
+                           int64_t plane, const double ref[2], hipStream_t s) {
+    const int g = site_grid((int64_t)nx * ny * nz);
+    LBM_DISPATCH_PREC(prec, S,
+                      hipLaunchKernelGGL(set_pops_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<S *>(dst), links, f,
+                                         nx, ny, nz, plane, ref[0], ref[1]));
+    return hipGetLastError();
+}
+
+hipError_t launch_get_pops(int prec, const void *src, const uint32_t *links, double *f, int nx, int ny, int nz,
+                           int64_t plane, const double ref[2], hipStream_t s) {
+    const int g = site_grid((int64_t)nx * ny * nz);
+    LBM_DISPATCH_PREC(prec, S,
+                      hipLaunchKernelGGL(get_pops_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<const S *>(src),
+                                         links, f, nx, ny, nz, plane, ref[0], ref[1]));
+    return hipGetLastError();
+}
+
+}  // namespace lbm

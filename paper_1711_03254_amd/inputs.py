@@ -234,18 +234,29 @@ def pore_droplets(shape, sphere_centers: np.ndarray, sphere_radius: float, drop_
 
 def packed_spheres_case(n: int = 256, radius: float = 12.0, porosity: float = 0.40,
                         drop_radius: float = 4.0, drop_fraction: float = 0.01, seed: int = 3,
-                        minority: float = 0.03):
+                        minority: float = 0.03, interface_width: float = 0.0):
     """The 1 % mixture in packed spheres: a periodic cube of edge n filled with
     non-overlapping spheres of `radius` at the given porosity (solid mask),
     droplets of component A (radius `drop_radius`, `drop_fraction` of the
-    pore volume) in a carrier of component B.  Returns (solid, rho_A, rho_B,
-    info)."""
+    pore volume) in a carrier of component B.  With interface_width w > 0 the
+    droplet profile is 1/2 (1 - tanh((d - R) / w)) in the distance d from the
+    nearest droplet centre instead of a sharp step.  Returns (solid, rho_A,
+    rho_B, info)."""
     shape = (n, n, n)
     centers = sphere_pack(n, radius, 1.0 - porosity, seed)
     drops, solid = pore_droplets(shape, centers, radius, drop_radius, drop_fraction, seed + 1)
     inA = voxelize_spheres(shape, drops, drop_radius).astype(bool) if len(drops) else np.zeros(shape, bool)
-    rA = np.where(inA, 1.0, minority)
-    rB = np.where(inA, minority, 1.0)
+    if interface_width > 0 and len(drops):
+        from scipy.spatial import cKDTree
+        z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+        pts = np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(np.float64)
+        d, _ = cKDTree(np.mod(drops, n), boxsize=n).query(pts)
+        phi = (0.5 * (1.0 - np.tanh((d - drop_radius) / interface_width))).reshape(shape)
+        rA = minority + (1.0 - minority) * phi
+        rB = minority + (1.0 - minority) * (1.0 - phi)
+    else:
+        rA = np.where(inA, 1.0, minority)
+        rB = np.where(inA, minority, 1.0)
     rA[solid == 1] = 0.0
     rB[solid == 1] = 0.0
     info = {"spheres": int(len(centers)), "droplets": int(len(drops)),

@@ -1,0 +1,355 @@
+"""GPU <-> oracle parity through the C ABI (needs an MI355X: -m gpu).
+
+Tolerances: populations and densities in the normalized max-norm
+max|X_gpu - X_oracle| / max|X_oracle|; the velocity u_F as an absolute error
+in lattice units (its scale is the lattice speed; normalizing by max |u_F|
+would divide by a spurious current of 1e-3 in a static droplet).
+FP64 storage and arithmetic 1e-12; FP32 1e-5 up to ten steps.  The FP64
+kernel and the oracle evaluate the same equations in a different order (and
+with fused multiply-adds on the GPU), so they agree to rounding, about 1e-15
+per step.  FP32 rounds every stored population to single precision (relative
+2^-24) and computes in FP32, so over n steps a deviation can grow to about
+n * 2 * 2^-24 of the population scale.  Longer FP32 runs use that bound: for
+the densities relative to their maximum, and for u_F as an absolute error in
+lattice units (u_F = j / rho inherits the absolute rounding of j, not a
+rounding relative to max |u_F|, which may be a tiny spurious current).
+Measured deviations are appended to $PARITY_LOG (JSON lines) when it is set.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1711_03254_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def fp32_bound(steps):
+    return max(1e-5, steps * 2 * 2.0 ** -24)
+
+
+def record(name, **vals):
+    path = os.environ.get("PARITY_LOG")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps({"test": name, **vals}) + "\n")
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU (run them with -m gpu on an MI355X)"
+    import paper_1711_03254_amd.lbm as m
+    m.load_library()
+    return m
+
+
+def nmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def ragged_case(seed=7, shape=(29, 37, 70), frac=0.08):
+    solid = inputs.random_mask(shape, frac, seed)
+    solid[:, 0, :] = 1                       # a wall plane as well
+    f0 = inputs.random_populations(shape, seed + 1)
+    f0[:, :, solid == 1] = 0.0
+    return solid, f0
+
+
+def gpu_ctx(lbm, shape, prec, solid, **kw):
+    nz, ny, nx = shape
+    r = np.ones(shape)
+    r[solid == 1] = 0.0 if solid is not None else 1.0
+    return lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(r, r.copy()), **kw))
+
+
+PHYS = dict(tau=(0.62, 1.7), G=-3.0, g=(1e-5, -2e-5, 3e-5), rho_s=0.3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("tile", [(64, 4), (32, 8), (16, 16), (8, 32)])
+@pytest.mark.parametrize("eq_kind,force_kind", [(0, 0), (1, 0), (0, 1)])
+def test_one_step_from_random_state(lbm, ora, prec, tile, eq_kind, force_kind):
+    """One step from seeded random populations on a 70 x 37 x 29 lattice
+    (ragged against every tile shape) with random solids and a wall plane:
+    all 38 populations of every site."""
+    solid, f0 = ragged_case()
+    shape = f0.shape[2:]
+    nz, ny, nx = shape
+    kw = dict(PHYS, eq_kind=eq_kind, force_kind=force_kind)
+    ctx = gpu_ctx(lbm, shape, prec, solid, tile=tile, zchunk=5, **kw)
+    lbm.lbm_set_populations(ctx, f0)
+    if prec == "fp64":
+        assert np.array_equal(lbm.lbm_get_populations(ctx), f0)
+    lbm.lbm_step(ctx, 1)
+    got = lbm.lbm_get_populations(ctx)
+    p = ora.Params(nx, ny, nz, solid=solid, **kw)
+    want = ora.step(p, f0)
+    dev = nmax(got, want)
+    record("one_step_random", prec=prec, tile=list(tile), eq_kind=eq_kind, force_kind=force_kind, dev=dev)
+    assert dev <= TOL[prec]
+    assert np.all(got[:, :, solid == 1] == 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_moments_and_reduce_match(lbm, ora, prec):
+    solid, f0 = ragged_case(seed=11)
+    shape = f0.shape[2:]
+    nz, ny, nx = shape
+    ctx = gpu_ctx(lbm, shape, prec, solid, **PHYS)
+    lbm.lbm_set_populations(ctx, f0)
+    p = ora.Params(nx, ny, nz, solid=solid, **PHYS)
+    g1, g2, gu = lbm.lbm_moments(ctx)
+    o1, o2, ou = ora.moments(p, f0)
+    assert nmax(g1, o1) <= TOL[prec] and nmax(g2, o2) <= TOL[prec] and nmax(gu, ou) <= TOL[prec]
+    gr = lbm.lbm_reduce(ctx)
+    orr = ora.reduce(p, f0)
+    np.testing.assert_allclose(gr[:2], orr[:2], rtol=TOL[prec])
+    np.testing.assert_allclose(gr[2:], orr[2:], rtol=0, atol=TOL[prec] * (orr[0] + orr[1]))
+
+
+@pytest.mark.parametrize("eq_kind", [0, 1])
+def test_init_equals_oracle_equilibrium(lbm, ora, eq_kind):
+    shape = (12, 10, 17)
+    nz, ny, nx = shape
+    solid = inputs.random_mask(shape, 0.1, 3)
+    r1 = inputs.smooth_random_density(shape, 4, mean=0.6, amp=0.3)
+    r2 = 1.1 - r1
+    u = 0.05 * (inputs.uniform(5, 3 * r1.size).reshape((3,) + shape) - 0.5)
+    r1[solid == 1] = 0
+    r2[solid == 1] = 0
+    ctx = lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.LBM_FP64, solid=solid, rho_init=(r1, r2), u_init=u,
+                                  eq_kind=eq_kind))
+    p = ora.Params(nx, ny, nz, solid=solid, eq_kind=eq_kind)
+    assert nmax(lbm.lbm_get_populations(ctx), ora.init(p, r1, r2, u)) <= 1e-14
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_droplet_500_steps(lbm, droplet_reference, prec):
+    rA, rB, p, ref, (red0, red500) = droplet_reference
+    ctx = lbm.lbm_init(lbm.Params(32, 32, 32, prec=lbm.PRECISIONS[prec], tau=p.tau, G=p.G, rho_init=(rA, rB),
+                                  check_every=50))
+    lbm.lbm_step(ctx, 10)
+    d10 = [nmax(k, o) for k, o in zip(lbm.lbm_moments(ctx), ref[10])]
+    lbm.lbm_step(ctx, 490)
+    got = lbm.lbm_moments(ctx)
+    d500 = [nmax(k, o) for k, o in zip(got, ref[500])]
+    uabs = float(np.abs(got[2] - ref[500][2]).max())
+    record("droplet_32", prec=prec, dev10=d10, dev500=d500, u_abs500=uabs)
+    assert max(d10) <= TOL[prec]
+    bound = TOL[prec] if prec == "fp64" else fp32_bound(500)
+    assert max(d500[:2]) <= bound and uabs <= bound
+    red = lbm.lbm_reduce(ctx)
+    # mass conservation: FP64 to rounding, FP32 to its storage precision
+    drift = np.abs(red[:2] - red0[:2]) / red0[:2]
+    assert drift.max() <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+def test_checkpoint_resume_is_bitwise(lbm):
+    solid, f0 = ragged_case(seed=21)
+    shape = f0.shape[2:]
+    for prec in ("fp64", "fp32"):
+        a = gpu_ctx(lbm, shape, prec, solid, **PHYS)
+        lbm.lbm_set_populations(a, f0)
+        lbm.lbm_step(a, 7)
+        mid = lbm.lbm_get_populations(a)
+        lbm.lbm_step(a, 6)
+        end_a = lbm.lbm_get_populations(a)
+        b = gpu_ctx(lbm, shape, prec, solid, **PHYS)
+        lbm.lbm_set_populations(b, mid)
+        lbm.lbm_step(b, 6)
+        assert np.array_equal(lbm.lbm_get_populations(b), end_a)
+
+
+def test_runs_are_deterministic_and_tiles_agree(lbm):
+    solid, f0 = ragged_case(seed=31)
+    shape = f0.shape[2:]
+    outs = []
+    for tile in [(64, 4), (64, 4), (32, 8), (8, 32)]:
+        c = gpu_ctx(lbm, shape, "fp32", solid, tile=tile, **PHYS)
+        lbm.lbm_set_populations(c, f0)
+        lbm.lbm_step(c, 9)
+        outs.append(lbm.lbm_get_populations(c))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_translation_commutes_bitwise(lbm):
+    solid, f0 = ragged_case(seed=41, shape=(20, 24, 33))
+    shape = f0.shape[2:]
+    sh = (3, -5, 11)
+    a = gpu_ctx(lbm, shape, "fp64", solid, **PHYS)
+    lbm.lbm_set_populations(a, f0)
+    lbm.lbm_step(a, 4)
+    b = gpu_ctx(lbm, shape, "fp64", np.roll(solid, sh, axis=(0, 1, 2)).copy(), **PHYS)
+    lbm.lbm_set_populations(b, np.roll(f0, sh, axis=(2, 3, 4)).copy())
+    lbm.lbm_step(b, 4)
+    assert np.array_equal(np.roll(lbm.lbm_get_populations(a), sh, axis=(2, 3, 4)), lbm.lbm_get_populations(b))
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 3, 3), (1, 40, 1), (48, 48, 1), (5, 1, 70), (2, 130, 9)])
+def test_degenerate_and_thin_lattices(lbm, ora, shape):
+    """Lattices of extent 1 or 2 in some direction (every neighbour wraps onto
+    the site itself or its twin), nx = 1 with the 8 x 32 tile, wide rows."""
+    nz, ny, nx = shape
+    f0 = inputs.random_populations(shape, 51)
+    solid = None
+    if ny >= 9:
+        solid = np.zeros(shape, np.uint8)
+        solid[:, 0, :] = 1
+        f0[:, :, solid == 1] = 0.0
+    ctx = gpu_ctx(lbm, shape, "fp64", solid if solid is not None else np.zeros(shape, np.uint8), **PHYS)
+    lbm.lbm_set_populations(ctx, f0)
+    lbm.lbm_step(ctx, 3)
+    p = ora.Params(nx, ny, nz, solid=solid, **PHYS)
+    assert nmax(lbm.lbm_get_populations(ctx), ora.run(p, f0, 3)) <= 1e-12
+
+
+def test_zero_steps_is_a_no_op(lbm):
+    solid, f0 = ragged_case(seed=61, shape=(6, 9, 10))
+    c = gpu_ctx(lbm, f0.shape[2:], "fp64", solid, **PHYS)
+    lbm.lbm_set_populations(c, f0)
+    lbm.lbm_step(c, 0)
+    assert np.array_equal(lbm.lbm_get_populations(c), f0)
+    assert lbm.lbm_info(c)["steps_done"] == 0
+
+
+def test_error_paths(lbm):
+    shape = (8, 8, 8)
+    r = np.ones(shape)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_init(lbm.Params(8, 8, 8, rho_init=(r, r), solid=np.ones(shape, np.uint8)))
+    assert e.value.code == lbm.LBM_EINVAL and "no fluid" in str(e.value)
+    bad = r.copy()
+    bad[1, 2, 3] = -0.1
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_init(lbm.Params(8, 8, 8, rho_init=(bad, r)))
+    assert e.value.code == lbm.LBM_EINVAL
+    # a NaN planted in the state is caught by the periodic check
+    c = lbm.lbm_init(lbm.Params(8, 8, 8, rho_init=(r, r), check_every=4))
+    f = lbm.lbm_get_populations(c)
+    f[0, 3, 4, 4, 4] = np.nan
+    lbm.lbm_set_populations(c, f)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_step(c, 10)
+    assert e.value.code == lbm.LBM_ENONFINITE
+    assert lbm.lbm_info(c)["steps_done"] == 4
+    # an impossible mass tolerance trips the drift check
+    rA, rB = inputs.droplet(shape, 2.5)
+    c = lbm.lbm_init(lbm.Params(8, 8, 8, rho_init=(rA, rB), G=-3.0, check_every=3, mass_tol=1e-300))
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_step(c, 30)
+    assert e.value.code == lbm.LBM_EMASSDRIFT
+
+
+def test_device_pointers_and_stream(lbm, ora):
+    """Inputs and outputs as torch tensors on the GPU, on a torch stream."""
+    import torch
+    shape = (16, 12, 20)
+    nz, ny, nx = shape
+    rA, rB = inputs.droplet(shape, 4.0)
+    s = torch.cuda.Stream()
+    dA = torch.from_numpy(rA).cuda()
+    dB = torch.from_numpy(rB).cuda()
+    torch.cuda.synchronize()
+    ctx = lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.LBM_FP64, G=-3.0, rho_init=(dA, dB), stream=s))
+    lbm.lbm_step(ctx, 5)
+    o1 = torch.empty(shape, dtype=torch.float64, device="cuda")
+    o2 = torch.empty(shape, dtype=torch.float64, device="cuda")
+    ou = torch.empty((3,) + shape, dtype=torch.float64, device="cuda")
+    lbm.lbm_moments(ctx, o1, o2, ou)
+    p = ora.Params(nx, ny, nz, G=-3.0)
+    w1, w2, wu = ora.moments(p, ora.run(p, ora.init(p, rA, rB), 5))
+    assert nmax(o1.cpu().numpy(), w1) <= 1e-12 and nmax(ou.cpu().numpy(), wu) <= 1e-12
+    fd = torch.empty((2, 19) + shape, dtype=torch.float64, device="cuda")
+    lbm.lbm_get_populations(ctx, fd)
+    assert np.array_equal(fd.cpu().numpy(), lbm.lbm_get_populations(ctx))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nuA,nuB", [(0.0017, 1.7), (1.7, 0.0017), (0.0017, 0.17), (0.0017, 0.017)])
+def test_two_layer_channel_20000_steps(lbm, ora, prec, nuA, nuB):
+    """The two-layer channel workload: 8 x 64 x 256, walls at y = 0 and 63,
+    A in y = 1..31 and B in y = 32..62 with minority densities near their
+    coexistence value, g = 1e-6 along z, G = -4.2, viscosity ratios 1000,
+    1/1000, 100 and 10 with the lower viscosity 0.0017 (tau = 0.5051),
+    20000 steps.  The state stays uniform in x and z, so the oracle runs the
+    exactly equivalent 1 x 64 x 1 column."""
+    T0 = 1.0 / 3.0
+    nz, ny, nx = 256, 64, 8
+    kw = dict(tau=(nuA / T0 + 0.5, nuB / T0 + 0.5), G=-4.2, g=(0.0, 0.0, 1e-6))
+    col = np.zeros((1, ny, 1), np.uint8)
+    col[0, 0, 0] = col[0, -1, 0] = 1
+    r1, r2 = inputs.two_layer((1, ny, 1), 1.0, 0.005)
+    r1[col == 1] = 0
+    r2[col == 1] = 0
+    ora.set_threads(1)
+    p = ora.Params(1, ny, 1, solid=col, **kw)
+    o1, o2, ou = ora.moments(p, ora.run(p, ora.init(p, r1, r2), 20000))
+    ora.set_threads(8)
+    shape = (nz, ny, nx)
+    solid = np.broadcast_to(col, shape).copy()
+    ctx = lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=solid,
+                                  rho_init=(np.broadcast_to(r1, shape).copy(), np.broadcast_to(r2, shape).copy()),
+                                  check_every=1000, **kw))
+    lbm.lbm_step(ctx, 20000)
+    g1, g2, gu = lbm.lbm_moments(ctx)
+    devs = [nmax(g1, np.broadcast_to(o1, shape)), nmax(g2, np.broadcast_to(o2, shape)),
+            nmax(gu, np.broadcast_to(ou, (3,) + shape))]
+    # x and z stay uniform on the GPU too
+    spread = float(np.abs(gu[2] - gu[2][:1, :, :1]).max() / np.abs(gu[2]).max())
+    uabs = float(np.abs(gu - np.broadcast_to(ou, (3,) + shape)).max())
+    record("channel_8x64x256", prec=prec, nuA=nuA, nuB=nuB, dev=devs, u_abs=uabs, xz_spread=spread)
+    bound = TOL[prec] if prec == "fp64" else fp32_bound(20000)
+    assert max(devs[:2]) <= bound and uabs <= bound
+    assert spread <= (1e-13 if prec == "fp64" else 1e-5)
+
+
+@pytest.fixture(scope="module")
+def packed_spheres():
+    """The benchmark workload: 256^3 packed spheres (radius 12, porosity
+    0.40), 1 % droplets of A, nu ratio 10, G = -4.2, g = 1e-6 along z,
+    rho^s = 0.25."""
+    solid, rA, rB, info = inputs.packed_spheres_case(n=256, radius=12.0, porosity=0.40, drop_radius=4.0,
+                                                     drop_fraction=0.01, seed=3, minority=0.03)
+    phys = dict(tau=(1.0 / 60.0 / (1.0 / 3.0) + 0.5, 1.0), G=-4.2, g=(0.0, 0.0, 1e-6), rho_s=0.25)
+    return solid, rA, rB, phys
+
+
+def test_full_size_sampled_sites(lbm, ora, packed_spheres):
+    """At the benchmark's full size and launch configuration (FP32, default
+    tile and z-chunk), two steps: the first from the known initial state, the
+    second from the GPU's own state after one step.  4000 seeded fluid sites
+    (half of them next to a wall) are recomputed one by one by the oracle."""
+    import torch
+    solid, rA, rB, phys = packed_spheres
+    n = solid.shape[0]
+    ctx = lbm.lbm_init(lbm.Params(n, n, n, prec=lbm.LBM_FP32, solid=solid, rho_init=(rA, rB), check_every=100,
+                                  **phys))
+    p = ora.Params(n, n, n, solid=solid, **phys)
+    fluid = np.flatnonzero(solid.ravel() == 0)
+    near = np.zeros(solid.shape, bool)
+    for ax in range(3):
+        for sh in (1, -1):
+            near |= np.roll(solid, sh, axis=ax) == 1
+    nearwall = np.flatnonzero((solid.ravel() == 0) & near.ravel())
+    pick = np.concatenate([fluid[(inputs.uniform(91, 2000) * len(fluid)).astype(np.int64)],
+                           nearwall[(inputs.uniform(92, 2000) * len(nearwall)).astype(np.int64)]])
+    f_prev = ora.init(p, rA, rB)
+    fd = torch.empty((2, 19) + solid.shape, dtype=torch.float64, device="cuda")
+    idx = torch.from_numpy(pick).cuda()
+    for step in range(2):
+        lbm.lbm_step(ctx, 1)
+        lbm.lbm_get_populations(ctx, fd)
+        got = fd.view(2, 19, -1)[:, :, idx].permute(2, 0, 1).cpu().numpy()
+        want = ora.step_sites(p, f_prev, pick)
+        dev = nmax(got, want)
+        record("packed_spheres_256_sampled", step=step + 1, dev=dev, sites=int(len(pick)))
+        assert dev <= TOL["fp32"]
+        if step == 0:
+            f_prev = fd.cpu().numpy()
+    del fd

@@ -1,0 +1,104 @@
+"""The precision form: populations stored as 16-bit deviations
+f_i - w_i rho_ref[a] (FP16S, BF16S) with FP32 arithmetic, against the FP64
+oracle (needs an MI355X: -m gpu).
+
+The paper fixes no precision, so the bounds are derived from the formats:
+a stored deviation d is rounded with relative error at most 2^-(p+1)
+(p = 10 significand bits for FP16, 7 for BF16), and since sum_i w_i = 1 a
+density built from 19 such values moves by at most 2^-(p+1) max|d / w|
+per rounding.  The tests assert those bounds and record the measured errors
+(PARITY_LOG), which are the figures to state.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1711_03254_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+UNIT = {"fp16s": 2.0 ** -11, "bf16s": 2.0 ** -8}
+
+
+def record(name, **vals):
+    path = os.environ.get("PARITY_LOG")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps({"test": name, **vals}) + "\n")
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1711_03254_amd.lbm as m
+    m.load_library()
+    return m
+
+
+def nmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+PHYS = dict(tau=(0.62, 1.7), G=-3.0, g=(1e-5, -2e-5, 3e-5), rho_s=0.3)
+
+
+@pytest.mark.parametrize("prec", ["fp16s", "bf16s"])
+def test_one_step_16bit(lbm, ora, prec):
+    """One step from a smooth near-equilibrium state with walls: the state is
+    rounded once on entry and once on store, so every population is within
+    2 x 2^-(p+1) of the largest stored deviation (plus the propagation of the
+    entry rounding through one step, bounded by the same amount)."""
+    shape = (20, 26, 70)
+    nz, ny, nx = shape
+    solid = inputs.random_mask(shape, 0.05, 71)
+    solid[:, 0, :] = 1
+    r1 = inputs.smooth_random_density(shape, 72, mean=0.5, amp=0.3)
+    r2 = 1.05 - r1
+    u = 0.04 * (inputs.uniform(73, 3 * r1.size).reshape((3,) + shape) - 0.5)
+    r1[solid == 1] = 0
+    r2[solid == 1] = 0
+    p = ora.Params(nx, ny, nz, solid=solid, **PHYS)
+    f0 = ora.init(p, r1, r2, u)
+    ctx = lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(r1, r2), u_init=u,
+                                  **PHYS))
+    got0 = lbm.lbm_get_populations(ctx)
+    lbm.lbm_step(ctx, 1)
+    got = lbm.lbm_get_populations(ctx)
+    want = ora.step(p, f0)
+    _, w, _ = ora.lattice()
+    ref = np.array([r1[solid == 0].mean(), r2[solid == 0].mean()])
+    dev_scale = np.abs(f0 - w[None, :, None, None, None] * ref[:, None, None, None, None]).max()
+    e_in = float(np.abs(got0 - f0).max())
+    e_out = float(np.abs(got - want).max())
+    record("one_step_16bit", prec=prec, entry_abs=e_in, step_abs=e_out, dev_scale=float(dev_scale),
+           step_rel=nmax(got, want))
+    assert e_in <= UNIT[prec] * dev_scale * 1.0001
+    assert e_out <= 4 * UNIT[prec] * dev_scale
+
+
+@pytest.mark.parametrize("prec", ["fp16s", "bf16s"])
+def test_droplet_16bit_against_fp64(lbm, droplet_reference, prec):
+    """The 32^3 droplet, 500 steps in 16-bit storage against the FP64 oracle:
+    the densities' error and the mass drift, stated; asserted against the
+    per-step rounding bound accumulated over the run."""
+    rA, rB, p, ref, (red0, _) = droplet_reference
+    ctx = lbm.lbm_init(lbm.Params(32, 32, 32, prec=lbm.PRECISIONS[prec], tau=p.tau, G=p.G, rho_init=(rA, rB),
+                                  check_every=100))
+    lbm.lbm_step(ctx, 10)
+    m10 = lbm.lbm_moments(ctx)
+    lbm.lbm_step(ctx, 490)
+    m500 = lbm.lbm_moments(ctx)
+    red = lbm.lbm_reduce(ctx)
+    d10 = [nmax(m10[0], ref[10][0]), nmax(m10[1], ref[10][1]), float(np.abs(m10[2] - ref[10][2]).max())]
+    d500 = [nmax(m500[0], ref[500][0]), nmax(m500[1], ref[500][1]), float(np.abs(m500[2] - ref[500][2]).max())]
+    drift = (np.abs(red[:2] - red0[:2]) / red0[:2]).tolist()
+    record("droplet_32_16bit", prec=prec, dev10=d10, dev500=d500, mass_drift=drift)
+    # the largest deviation stored is ~ w_i |rho - rho_ref| <= w_i; per step the
+    # densities move by at most UNIT[prec] of it
+    assert max(d10) <= 10 * UNIT[prec]
+    assert max(d500) <= 500 * UNIT[prec]
+    assert max(drift) <= 500 * UNIT[prec]
+    assert np.isfinite(m500[2]).all()
