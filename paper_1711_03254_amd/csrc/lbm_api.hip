@@ -302,9 +302,11 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
     if (c->p.mass_tol == 0) c->p.mass_tol = default_mass_tol(p.prec);
     c->N = (int64_t)p.nx * p.ny * p.nz;
     c->esz = esz;
-    c->plane = (c->N + 127) / 128 * 128;   // each plane starts 256-byte aligned
-    if (2 * (uint64_t)c->plane * esz >= (1ull << 32)) {
-        int rc = fail(nullptr, LBM_EINVAL, "lattice too large: one population plane must stay below 2 GiB");
+    // Each plane starts 256-byte aligned; the odd padding keeps the 38 planes
+    // of a buffer from starting at the same offsets modulo large powers of two.
+    c->plane = (c->N + 127) / 128 * 128 + 128 * 13;
+    if (2 * (uint64_t)c->plane * esz >= (1ull << 31)) {
+        int rc = fail(nullptr, LBM_EINVAL, "lattice too large: one population plane must stay below 1 GiB");
         delete c;
         return rc;
     }

@@ -133,6 +133,37 @@ __device__ __forceinline__ void plane_offsets(int z, int nz, uint32_t nxy_bytes,
     sz[2] = (uint32_t)zm * nxy_bytes;
 }
 
+// Raw buffer access.  A buffer resource bounds every load: an offset at or
+// beyond num_records returns 0 without touching memory, which is how lanes
+// without work (solid sites, no ring site) keep the issue branch-free.
+constexpr int kRsrcWord3 = 0x00020000;   // gfx9 raw buffer, bounds-checked in bytes
+constexpr uint32_t kNoLoad = 0xffffffffu;
+
+template <typename S> __device__ __forceinline__ S buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ __half buf_load<__half>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ __hip_bfloat16 buf_load<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(__hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+
+// Write-once streaming store of the post-collision populations (they are
+// read again only in the next step, so they should not displace the reused
+// lines from the caches).
+template <typename S> __device__ __forceinline__ void stream_store(S *p, S v) {
+    if constexpr (std::is_same_v<S, float> || std::is_same_v<S, double>) {
+        __builtin_nontemporal_store(v, p);
+    } else {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), reinterpret_cast<unsigned short *>(p));
+    }
+}
+
 // Pull of one fluid site: f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) when the
 // link bit i says x - c_i is solid.  The two members of an opposite pair
 // (odd i, i + 1) are addressed from the odd member's plane, so a reversed
@@ -145,28 +176,25 @@ __device__ __forceinline__ void issue_pull(const KArgs<S> &a, const Column &col,
     const char *base = reinterpret_cast<const char *>(a.src);
     const uint32_t pb = a.plane_bytes;
     const uint32_t self = col.xy[4] + sz[1];
-    // An inactive lane (a solid site, or no ring site) reads the first element
-    // of each plane instead: always in bounds, a cache hit after the first
-    // lane, and the issue stays free of branches.
-    const uint32_t on = active ? 0xffffffffu : 0u;
     sfor<19>([&](auto I) {
         constexpr int i = I;
+        constexpr int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);   // odd member of the pair
         uint32_t off;
-        const char *p;
         if constexpr (i == 0) {
             off = self;
-            p = base;
         } else {
-            constexpr int lo = (i & 1) ? i : i - 1;   // odd member of the pair
             const uint32_t stream = col.xy[(cy_of(i) + 1) * 3 + cx_of(i) + 1] + sz[cz_of(i) + 1];
             const bool wall = (L >> i) & 1u;
             if constexpr (i == lo) off = wall ? self + pb : stream;
             else off = wall ? self : stream + pb;
-            p = base + (size_t)lo * pb;
         }
-        off &= on;
-        raw[0][i] = *reinterpret_cast<const S *>(p + off);
-        raw[1][i] = *reinterpret_cast<const S *>(p + (size_t)19 * pb + off);
+        off = active ? off : kNoLoad;
+        const char *p = base + (size_t)lo * pb;
+        const __amdgpu_buffer_rsrc_t r0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), 0, (int)(2 * pb), kRsrcWord3);
+        const __amdgpu_buffer_rsrc_t r1 =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p + (size_t)19 * pb), 0, (int)(2 * pb), kRsrcWord3);
+        raw[0][i] = buf_load<S>(r0, off);
+        raw[1][i] = buf_load<S>(r1, off);
     });
 }
 
@@ -437,7 +465,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                 const uint32_t sofs = ci.xy[4] + (uint32_t)z * nxyB;
                 auto put = [&](int d, int i, C v) {
                     if constexpr (Codec<S>::shifted) v -= C(w_of(i)) * (d == 0 ? ref0 : ref1);
-                    *reinterpret_cast<S *>(dbase + (size_t)(d * 19 + i) * pb + sofs) = Codec<S>::st(v);
+                    stream_store<S>(reinterpret_cast<S *>(dbase + (size_t)(d * 19 + i) * pb + sofs), Codec<S>::st(v));
                 };
 #pragma unroll
                 for (int d = 0; d < 2; ++d)

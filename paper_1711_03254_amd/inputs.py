@@ -263,3 +263,39 @@ def packed_spheres_case(n: int = 256, radius: float = 12.0, porosity: float = 0.
             "porosity": float((solid == 0).mean()),
             "drop_fraction_of_pore": float(inA.sum() / max(1, (solid == 0).sum()))}
     return solid, rA, rB, info
+
+
+def ensemble_case(count: int = 64, seed: int = 11, nu_min: float = 0.0017, g: float = 1e-6):
+    """The batched ensemble: `count` square ducts (solid faces at the x and y
+    edges, periodic along z) with a slug front -- A in z < nz/2, B above.
+    Seeded draws: nx = ny uniform in {48, 64, ..., 128}, nz uniform in
+    {96, 112, ..., 256}; viscosity ratio log-uniform in [1, 1000] with the
+    lower viscosity nu_min (A is the less viscous component); the workloads'
+    G uniform in [1.2, 1.6], returned in the paper's sign and weights as
+    G = -3 G_w; contact angle uniform in [30, 150] degrees, mapped to the wall
+    parameter linearly, rho^s = 0.4 cos(theta) / cos(30 deg) (an uncalibrated
+    stand-in: 90 degrees is the neutral wall).  Returns a list of dicts with
+    shape (nz, ny, nx), solid, rho_A, rho_B and the physical parameters."""
+    r = uniform(seed, 6 * count).reshape(count, 6)
+    T0 = 1.0 / 3.0
+    out = []
+    for k in range(count):
+        n = 48 + 16 * int(r[k, 0] * 6)
+        nz = 96 + 16 * int(r[k, 1] * 11)
+        ratio = 10.0 ** (3.0 * r[k, 2])
+        Gw = 1.2 + 0.4 * r[k, 3]
+        theta = math.radians(30.0 + 120.0 * r[k, 4])
+        rho_s = 0.4 * math.cos(theta) / math.cos(math.radians(30.0))
+        shape = (nz, n, n)
+        solid = np.zeros(shape, np.uint8)
+        solid[:, 0, :] = solid[:, -1, :] = 1
+        solid[:, :, 0] = solid[:, :, -1] = 1
+        z = np.arange(nz)[:, None, None] * np.ones(shape)
+        rA = np.where(z < nz // 2, 1.0, 0.03)
+        rB = np.where(z < nz // 2, 0.03, 1.0)
+        rA[solid == 1] = 0.0
+        rB[solid == 1] = 0.0
+        out.append({"shape": shape, "solid": solid, "rho_A": rA, "rho_B": rB,
+                    "tau": (nu_min / T0 + 0.5, nu_min * ratio / T0 + 0.5), "G": -3.0 * Gw,
+                    "g": (0.0, 0.0, g), "rho_s": rho_s, "ratio": ratio, "theta_deg": math.degrees(theta)})
+    return out

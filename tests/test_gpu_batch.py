@@ -1,0 +1,112 @@
+"""Batched stepping of many uneven domains and graph replay (needs an
+MI355X: -m gpu).  A batch advances every domain with one launch per step over
+a work list of all their tiles; runs of plain steps replay a captured HIP
+graph.  Each domain's result must be bit for bit the result of stepping it
+alone, one launch at a time."""
+import numpy as np
+import pytest
+
+from paper_1711_03254_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+T0 = 1.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1711_03254_amd.lbm as m
+    m.load_library()
+    return m
+
+
+def duct_case(shape, seed, nu_ratio, G, rho_s):
+    """A square duct along z (solid faces at x and y edges) with a slug of
+    A in the lower half of z, B above."""
+    nz, ny, nx = shape
+    solid = np.zeros(shape, np.uint8)
+    solid[:, 0, :] = solid[:, -1, :] = 1
+    solid[:, :, 0] = solid[:, :, -1] = 1
+    z = np.arange(nz)[:, None, None] * np.ones(shape)
+    rA = np.where(z < nz // 2, 1.0, 0.05)
+    rB = np.where(z < nz // 2, 0.05, 1.0)
+    rA[solid == 1] = 0
+    rB[solid == 1] = 0
+    nu_min = 0.02
+    tau = (nu_min / T0 + 0.5, nu_min * nu_ratio / T0 + 0.5)
+    return solid, rA, rB, dict(tau=tau, G=G, g=(0.0, 0.0, 1e-5), rho_s=rho_s)
+
+
+CASES = [((40, 24, 24), 1, 1.0, -3.0, 0.2), ((56, 16, 32), 2, 10.0, -3.3, -0.3), ((24, 40, 16), 3, 30.0, -2.8, 0.0),
+         ((33, 17, 20), 4, 3.0, -3.1, 0.4), ((16, 16, 16), 5, 100.0, -3.0, 0.1)]
+
+
+def make(lbm, prec, case, check_every=0, tile=(32, 8)):
+    shape, seed, ratio, G, rs = case
+    solid, rA, rB, phys = duct_case(shape, seed, ratio, G, rs)
+    nz, ny, nx = shape
+    return lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(rA, rB),
+                                   check_every=check_every, tile=tile, **phys))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("nsteps", [1, 7, 37])
+def test_batch_equals_single_domains(lbm, prec, nsteps):
+    singles = [make(lbm, prec, c) for c in CASES]
+    for c in singles:
+        for _ in range(nsteps):
+            lbm.lbm_step(c, 1)
+    batched = [make(lbm, prec, c, check_every=(5 if k % 2 else 0)) for k, c in enumerate(CASES)]
+    b = lbm.lbm_batch_create(batched)
+    lbm.lbm_batch_step(b, nsteps)
+    for s, d in zip(singles, batched):
+        assert np.array_equal(lbm.lbm_get_populations(s), lbm.lbm_get_populations(d))
+        assert lbm.lbm_info(d)["steps_done"] == nsteps
+    # the domains stay usable on their own, and a second batch call continues them
+    lbm.lbm_step(batched[0], 3)
+    lbm.lbm_batch_step(b, 5)
+    for c in singles:
+        lbm.lbm_step(c, 5)
+    lbm.lbm_step(singles[0], 3)
+    for s, d in zip(singles, batched):
+        assert np.array_equal(lbm.lbm_get_populations(s), lbm.lbm_get_populations(d))
+
+
+def test_graph_replay_equals_single_launches(lbm):
+    case = CASES[1]
+    a = make(lbm, "fp32", case)
+    b = make(lbm, "fp32", case)
+    lbm.lbm_step(a, 53)           # three graph replays and five single launches
+    for _ in range(53):
+        lbm.lbm_step(b, 1)
+    assert np.array_equal(lbm.lbm_get_populations(a), lbm.lbm_get_populations(b))
+    c = make(lbm, "fp32", case, check_every=20)
+    lbm.lbm_step(c, 53)
+    assert np.array_equal(lbm.lbm_get_populations(c), lbm.lbm_get_populations(a))
+
+
+def test_batch_check_names_the_failing_domain(lbm):
+    ctxs = [make(lbm, "fp32", c, check_every=4) for c in CASES[:3]]
+    f = lbm.lbm_get_populations(ctxs[2])
+    shape = f.shape[2:]
+    f[0, 0, shape[0] // 2, shape[1] // 2, shape[2] // 2] = np.nan
+    lbm.lbm_set_populations(ctxs[2], f)
+    b = lbm.lbm_batch_create(ctxs)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_batch_step(b, 12)
+    assert e.value.code == lbm.LBM_ENONFINITE and "domain 2" in str(e.value)
+
+
+def test_batch_rejects_mixed_contexts(lbm):
+    a = make(lbm, "fp32", CASES[0])
+    b = make(lbm, "fp64", CASES[1])
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_batch_create([a, b])
+    assert e.value.code == lbm.LBM_EINVAL
+    c = make(lbm, "fp32", CASES[1], tile=(16, 16))
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_batch_create([a, c])
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_batch_create([a, a])
