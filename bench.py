@@ -52,7 +52,9 @@ def kernel_hash():
 
 
 def time_precision(lbm, torch, prec, solid, rA, rB, phys, steps, warmup, check_every):
-    stream = torch.cuda.current_stream()
+    # The library launches on the stream it is given; events are recorded on
+    # that same stream so that they bracket its kernels.
+    stream = torch.cuda.Stream()
     n = solid.shape[0]
     ctx = lbm.lbm_init(lbm.Params(n, n, n, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(rA, rB),
                                   check_every=check_every, stream=stream, **phys))
@@ -136,6 +138,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--G", type=float, default=-4.2)
     ap.add_argument("--interface-width", type=float, default=1.5)
+    ap.add_argument("--no-all-fluid", dest="all_fluid", action="store_false",
+                    help="skip the all-fluid lattice of the same size")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -166,6 +170,21 @@ def main():
         k = args.steps if prec == "fp32" else max(50, args.steps // 2)
         res[prec] = time_precision(lbm, torch, prec, solid, rA, rB, phys, k, args.warmup, args.check_every)
         print(f"# {prec}: {json.dumps(res[prec])}", file=sys.stderr, flush=True)
+    # The same kernel on an all-fluid lattice of the same size (a droplet of
+    # A in B, no solids): its bandwidth fraction without the geometry's
+    # solid sites, which the dense layout still stores and sweeps.
+    allf = {}
+    if args.all_fluid:
+        import numpy as np
+        from paper_1711_03254_amd import inputs
+        n = args.size
+        dA, dB = inputs.droplet((n, n, n), n / 6.4)
+        zero = np.zeros((n, n, n), np.uint8)
+        phys_af = dict(tau=(1.0, 1.0), G=-3.0, g=(0.0, 0.0, 0.0), rho_s=0.0)
+        for prec in ("fp32", "fp16s"):
+            r = time_precision(lbm, torch, prec, zero, dA, dB, phys_af, max(50, args.steps // 2), args.warmup, 0)
+            allf[prec] = {k: r[k] for k in ("kernel_ms", "kernel_mlups", "algorithmic_GBs", "hbm_frac")}
+            print(f"# all-fluid {prec}: {json.dumps(allf[prec])}", file=sys.stderr, flush=True)
     main_r = res["fp32"]
     n_fluid = main_r["n_fluid"]
     roof = {
@@ -207,6 +226,7 @@ def main():
         "hbm_frac": round(main_r["hbm_frac"], 4),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "all_fluid": {k: {kk: round(v, 4) for kk, v in r.items()} for k, r in allf.items()},
         "precisions": {k: {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()}
                        for k, r in res.items()},
     }

@@ -305,8 +305,9 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
     // Each plane starts 256-byte aligned; the odd padding keeps the 38 planes
     // of a buffer from starting at the same offsets modulo large powers of two.
     c->plane = (c->N + 127) / 128 * 128 + 128 * 13;
-    if (2 * (uint64_t)c->plane * esz >= (1ull << 31)) {
-        int rc = fail(nullptr, LBM_EINVAL, "lattice too large: one population plane must stay below 1 GiB");
+    // The step addresses a component's 19 planes with 32-bit byte offsets.
+    if (19 * (uint64_t)c->plane * esz >= (1ull << 32)) {
+        int rc = fail(nullptr, LBM_EINVAL, "lattice too large: the 19 planes of one component must stay below 4 GiB");
         delete c;
         return rc;
     }

@@ -165,34 +165,30 @@ template <typename S> __device__ __forceinline__ void stream_store(S *p, S v) {
 }
 
 // Pull of one fluid site: f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) when the
-// link bit i says x - c_i is solid.  The two members of an opposite pair
-// (odd i, i + 1) are addressed from the odd member's plane, so a reversed
-// read is an offset of +- one plane and the choice is a select on a 32-bit
-// offset.  Only issues the 38 loads (raw storage values): a plane's interior
-// and ring loads are all in flight before any of them is consumed.
+// link bit i says x - c_i is solid.  One buffer resource spans each
+// component's 19 planes, so either choice is a 32-bit byte offset within it
+// and the bounce-back is a select.  Only issues the 38 loads (raw storage
+// values): a plane's interior and ring loads are all in flight before any of
+// them is consumed.
 template <typename S>
 __device__ __forceinline__ void issue_pull(const KArgs<S> &a, const Column &col, const uint32_t (&sz)[3], uint32_t L,
                                            bool active, S (&raw)[2][19]) {
-    const char *base = reinterpret_cast<const char *>(a.src);
-    const uint32_t pb = a.plane_bytes;
+    char *base = const_cast<char *>(reinterpret_cast<const char *>(a.src));
+    const uint32_t pb = a.plane_bytes, span = 19u * a.plane_bytes;
+    const __amdgpu_buffer_rsrc_t r0 = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)span, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t r1 = __builtin_amdgcn_make_buffer_rsrc(base + span, 0, (int)span, kRsrcWord3);
     const uint32_t self = col.xy[4] + sz[1];
     sfor<19>([&](auto I) {
         constexpr int i = I;
-        constexpr int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);   // odd member of the pair
         uint32_t off;
         if constexpr (i == 0) {
             off = self;
         } else {
-            const uint32_t stream = col.xy[(cy_of(i) + 1) * 3 + cx_of(i) + 1] + sz[cz_of(i) + 1];
+            const uint32_t stream = col.xy[(cy_of(i) + 1) * 3 + cx_of(i) + 1] + (sz[cz_of(i) + 1] + (uint32_t)i * pb);
             const bool wall = (L >> i) & 1u;
-            if constexpr (i == lo) off = wall ? self + pb : stream;
-            else off = wall ? self : stream + pb;
+            off = wall ? self + (uint32_t)opp_of(i) * pb : stream;
         }
         off = active ? off : kNoLoad;
-        const char *p = base + (size_t)lo * pb;
-        const __amdgpu_buffer_rsrc_t r0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), 0, (int)(2 * pb), kRsrcWord3);
-        const __amdgpu_buffer_rsrc_t r1 =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p + (size_t)19 * pb), 0, (int)(2 * pb), kRsrcWord3);
         raw[0][i] = buf_load<S>(r0, off);
         raw[1][i] = buf_load<S>(r1, off);
     });
@@ -378,7 +374,19 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
         load_plane(zwrap(z + 1), sp, true, zwrap(z + 2));
         __syncthreads();
 
-        if (inside && fluid_c) {
+        if (inside) {
+            // A solid site collides a harmless stand-in state so that the
+            // stores of every plane row cover whole cache lines (its values
+            // are never read: a pull from a solid site takes the bounce-back).
+            if (!fluid_c) {
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    mc[d].r = C(0.5);
+                    mc[d].jx = mc[d].jy = mc[d].jz = C(0);
+                    mc[d].xx = mc[d].yy = mc[d].zz = C(0.5) * T0;
+                    mc[d].xy = mc[d].xz = mc[d].yz = C(0);
+                }
+            }
             const C rho[2] = {mc[0].r, mc[1].r};
 
             // Eqs. (7), (11): sum_i w_i c_i psi'(x + c_i) from the LDS planes.
@@ -413,7 +421,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
             const C uz = (mc[0].jz + mc[1].jz + C(0.5) * (Fz[0] + Fz[1])) * inv;
             const C usq = ux * ux + uy * uy + uz * uz;
 
-            if constexpr (MODE == MODE_CHECK || MODE == MODE_MOMENTS) {
+            if constexpr (MODE == MODE_CHECK || MODE == MODE_MOMENTS) if (fluid_c) {
                 const bool ok = isfinite(rho[0]) && isfinite(rho[1]) && isfinite(ux) && isfinite(uy) && isfinite(uz);
                 acc[0] += (double)rho[0];
                 acc[1] += (double)rho[1];
@@ -422,7 +430,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                 acc[4] += (double)rho_t * (double)uz;
                 acc[5] += ok ? 0.0 : 1.0;
             }
-            if constexpr (MODE == MODE_MOMENTS) {
+            if constexpr (MODE == MODE_MOMENTS) if (fluid_c) {
                 const uint32_t s = ci.site + (uint32_t)z * nxy;
                 if (a.out_rho0) a.out_rho0[s] = (double)rho[0];
                 if (a.out_rho1) a.out_rho1[s] = (double)rho[1];
