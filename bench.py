@@ -157,10 +157,10 @@ def main():
         nel = int(args.copy_probe_gib * 2 ** 30 / 4)
         src = torch.ones(nel, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+        for _ in range(3):   # an elementwise kernel: reads nel * 4 bytes, writes nel * 4 bytes
+            torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
-        print(f"# copy probe: 3 copies of {nel * 4} bytes", file=sys.stderr, flush=True)
+        print(f"# copy probe: 3 elementwise copies of {nel * 4} bytes", file=sys.stderr, flush=True)
         del src, dst
 
     solid, rA, rB, info, phys = workload(args.size, args.G, args.interface_width)

@@ -133,73 +133,79 @@ __device__ __forceinline__ void plane_offsets(int z, int nz, uint32_t nxy_bytes,
     sz[2] = (uint32_t)zm * nxy_bytes;
 }
 
-// Raw buffer access.  A buffer resource bounds every load: an offset at or
-// beyond num_records returns 0 without touching memory, which is how lanes
-// without work (solid sites, no ring site) keep the issue branch-free.
-constexpr int kRsrcWord3 = 0x00020000;   // gfx9 raw buffer, bounds-checked in bytes
-constexpr uint32_t kNoLoad = 0xffffffffu;
+// Raw buffer access.  One buffer resource spans the 19 planes of one
+// component; the scalar offset selects a plane and the 32-bit lane offset a
+// site in it.  Every access issued is in bounds (lanes without work are
+// masked off), so the resource's range check never applies.
+constexpr int kRsrcWord3 = 0x00020000;   // gfx9 raw (unswizzled) buffer
+constexpr int kNonTemporal = 2;          // cache policy of the population stores
 
-template <typename S> __device__ __forceinline__ S buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
-template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-template <> __device__ __forceinline__ __half buf_load<__half>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
-}
-template <> __device__ __forceinline__ __hip_bfloat16 buf_load<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(__hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t component_rsrc(const void *base, int d, uint32_t pb) {
+    char *p = const_cast<char *>(static_cast<const char *>(base)) + (size_t)d * 19 * pb;
+    return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)(19u * pb), kRsrcWord3);
 }
 
-// Write-once streaming store of the post-collision populations (they are
-// read again only in the next step, so they should not displace the reused
-// lines from the caches).
-template <typename S> __device__ __forceinline__ void stream_store(S *p, S v) {
-    if constexpr (std::is_same_v<S, float> || std::is_same_v<S, double>) {
-        __builtin_nontemporal_store(v, p);
+template <typename S> __device__ __forceinline__ S buf_load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s);
+template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+}
+template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+}
+template <> __device__ __forceinline__ __half buf_load<__half>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+}
+template <>
+__device__ __forceinline__ __hip_bfloat16 buf_load<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(__hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+}
+
+// Write-once streaming store of a post-collision population (read again
+// only in the next step, so it should not displace reused lines).
+template <typename S> __device__ __forceinline__ void buf_store(S x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    if constexpr (std::is_same_v<S, float>) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, v, s, kNonTemporal);
+    } else if constexpr (std::is_same_v<S, double>) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v, s, kNonTemporal);
     } else {
-        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), reinterpret_cast<unsigned short *>(p));
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, kNonTemporal);
     }
 }
 
-// Pull of one fluid site: f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) when the
-// link bit i says x - c_i is solid.  One buffer resource spans each
-// component's 19 planes, so either choice is a 32-bit byte offset within it
-// and the bounce-back is a select.  Only issues the 38 loads (raw storage
-// values): a plane's interior and ring loads are all in flight before any of
-// them is consumed.
-template <typename S>
-__device__ __forceinline__ void issue_pull(const KArgs<S> &a, const Column &col, const uint32_t (&sz)[3], uint32_t L,
-                                           bool active, S (&raw)[2][19]) {
-    char *base = const_cast<char *>(reinterpret_cast<const char *>(a.src));
-    const uint32_t pb = a.plane_bytes, span = 19u * a.plane_bytes;
-    const __amdgpu_buffer_rsrc_t r0 = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)span, kRsrcWord3);
-    const __amdgpu_buffer_rsrc_t r1 = __builtin_amdgcn_make_buffer_rsrc(base + span, 0, (int)span, kRsrcWord3);
+// Pull of one site: f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) when link bit i
+// says x - c_i is solid (halfway bounce-back).  Both members of an opposite
+// pair (odd i, i + 1) are addressed from the odd member's plane, the scalar
+// offset, so the bounce-back is a select between two lane offsets.  WALLS =
+// false is the form for waves without any solid link.  Only issues the
+// loads: a plane's interior and ring loads are all in flight before any is
+// consumed.
+template <typename S, bool WALLS>
+__device__ __forceinline__ void issue_pull(__amdgpu_buffer_rsrc_t r0, __amdgpu_buffer_rsrc_t r1, const Column &col,
+                                           const uint32_t (&sz)[3], uint32_t pb, uint32_t L, S (&raw)[2][19]) {
     const uint32_t self = col.xy[4] + sz[1];
+    const uint32_t self_p = self + pb;
     sfor<19>([&](auto I) {
         constexpr int i = I;
+        constexpr int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+        const uint32_t soff = (uint32_t)lo * pb;
         uint32_t off;
         if constexpr (i == 0) {
             off = self;
         } else {
-            const uint32_t stream = col.xy[(cy_of(i) + 1) * 3 + cx_of(i) + 1] + (sz[cz_of(i) + 1] + (uint32_t)i * pb);
-            const bool wall = (L >> i) & 1u;
-            off = wall ? self + (uint32_t)opp_of(i) * pb : stream;
+            const uint32_t stream =
+                col.xy[(cy_of(i) + 1) * 3 + cx_of(i) + 1] + (sz[cz_of(i) + 1] + (i == lo ? 0u : pb));
+            if constexpr (WALLS) {
+                const bool wall = (L >> i) & 1u;
+                off = wall ? (i == lo ? self_p : self) : stream;
+            } else {
+                off = stream;
+            }
         }
-        off = active ? off : kNoLoad;
-        raw[0][i] = buf_load<S>(r0, off);
-        raw[1][i] = buf_load<S>(r1, off);
+        raw[0][i] = buf_load<S>(r0, off, soff);
+        raw[1][i] = buf_load<S>(r1, off, soff);
     });
-}
-
-template <typename S>
-__device__ __forceinline__ typename Codec<S>::C decode(S v, int i, typename Codec<S>::C ref) {
-    using C = typename Codec<S>::C;
-    C x = Codec<S>::ld(v);
-    if constexpr (Codec<S>::shifted) x += C(w_of(i)) * ref;
-    return x;
 }
 
 // Eq. (4) and the second moments of one component's pulled populations:
@@ -209,40 +215,152 @@ struct Moments {
     C r, jx, jy, jz, xx, yy, zz, xy, xz, yz;
 };
 
+// Adds s * v to an accumulator for a compile-time sign s in {-1, 0, 1}.
+// Accumulators start at -0, which the compiler drops from the first sum.
+template <int SGN, typename C> __device__ __forceinline__ void acc_signed(C &acc, C v) {
+    if constexpr (SGN > 0) acc += v;
+    if constexpr (SGN < 0) acc -= v;
+}
+
+// The moments from the sums s = f_i + f_opp(i) and differences
+// d = f_i - f_opp(i) of the nine opposite pairs: c_i c_i is even under
+// c -> -c and c_i odd, so each pair enters the second moments through s and
+// the first through d.  For the shifted 16-bit storage (values
+// f_i - w_i rho_ref) the shift is added back to the moments: sum_i w_i = 1,
+// sum_i w_i c_i = 0 and sum_i w_i c_i c_i = T0 I.
 template <typename S>
 __device__ __forceinline__ Moments<typename Codec<S>::C> moments_of(const S (&raw)[19], typename Codec<S>::C ref) {
     using C = typename Codec<S>::C;
-    Moments<C> m{C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
+    const C z = C(-0.0);
+    Moments<C> m{z, z, z, z, z, z, z, z, z, z};
+    m.r = Codec<S>::ld(raw[0]);
+    sfor<9>([&](auto K) {
+        constexpr int i = 2 * K + 1;
         constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
-        const C v = decode<S>(raw[i], i, ref);
-        m.r += v;
-        if constexpr (X > 0) { m.jx += v; m.xx += v; }
-        if constexpr (X < 0) { m.jx -= v; m.xx += v; }
-        if constexpr (Y > 0) { m.jy += v; m.yy += v; }
-        if constexpr (Y < 0) { m.jy -= v; m.yy += v; }
-        if constexpr (Z > 0) { m.jz += v; m.zz += v; }
-        if constexpr (Z < 0) { m.jz -= v; m.zz += v; }
-        if constexpr (X * Y > 0) m.xy += v;
-        if constexpr (X * Y < 0) m.xy -= v;
-        if constexpr (X * Z > 0) m.xz += v;
-        if constexpr (X * Z < 0) m.xz -= v;
-        if constexpr (Y * Z > 0) m.yz += v;
-        if constexpr (Y * Z < 0) m.yz -= v;
+        const C p = Codec<S>::ld(raw[i]), q = Codec<S>::ld(raw[i + 1]);
+        const C s = p + q, d = p - q;
+        m.r += s;
+        acc_signed<X>(m.jx, d);
+        acc_signed<Y>(m.jy, d);
+        acc_signed<Z>(m.jz, d);
+        acc_signed<X * X>(m.xx, s);
+        acc_signed<Y * Y>(m.yy, s);
+        acc_signed<Z * Z>(m.zz, s);
+        acc_signed<X * Y>(m.xy, s);
+        acc_signed<X * Z>(m.xz, s);
+        acc_signed<Y * Z>(m.yz, s);
     });
+    if constexpr (Codec<S>::shifted) {
+        const C t = C(1.0 / 3.0) * ref;
+        m.r += ref;
+        m.xx += t;
+        m.yy += t;
+        m.zz += t;
+    }
     return m;
 }
 
+// The density alone, summed in exactly the order of moments_of: a site's
+// density is the same bits whether a block pulls it as a tile site or as a
+// ring site of a neighbouring tile.
 template <typename S>
 __device__ __forceinline__ typename Codec<S>::C density_of(const S (&raw)[19], typename Codec<S>::C ref) {
     using C = typename Codec<S>::C;
-    C r = C(0);
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        r += decode<S>(raw[i], i, ref);
+    C r = Codec<S>::ld(raw[0]);
+    sfor<9>([&](auto K) {
+        constexpr int i = 2 * K + 1;
+        r += Codec<S>::ld(raw[i]) + Codec<S>::ld(raw[i + 1]);
     });
+    if constexpr (Codec<S>::shifted) r += ref;
     return r;
+}
+
+// 1 / x: the hardware reciprocal in single precision (1 ulp), a correctly
+// rounded division in double precision.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// s1 * a + s2 * b + s3 * c for compile-time signs in {-1, 0, 1}.
+template <int S1, int S2, int S3, typename C> __device__ __forceinline__ C dot_signed(C a, C b, C c) {
+    C r = C(-0.0);
+    acc_signed<S1>(r, a);
+    acc_signed<S2>(r, b);
+    acc_signed<S3>(r, c);
+    return r;
+}
+
+// Everything the collision of one component needs, per site.
+template <typename C>
+struct CompState {
+    C rho;            // rho_a
+    C Fx, Fy, Fz;     // F^a (Shan-Chen plus body force)
+    const Moments<C> *m;
+    C ref;            // shift of the 16-bit storage (0 otherwise)
+};
+
+// Eqs. (3), (9), (10) for one component: f*_i = w_i [rho P_i +
+// 4.5 (c_i c_i : X - T0 tr X) + 1.5 c_i . F] with X = (1 - 1/tau) Pi_neq +
+// guo (u_F F + F u_F), P_i = 1 + 3 cu + 4.5 cu^3 - 4.5 cu u^2 (R2 adds
+// 4.5 cu^2 - 1.5 u^2; r2 is 1 for R2, else 0).  Each opposite pair shares
+// the part E even under c -> -c and the odd part O:
+// f*_i = w (E + O), f*_opp(i) = w (E - O), with P_i split the same way
+// (peven, podd per pair).  The terms are scaled by the weights up front and
+// only the non-zero components of c_i enter.  `put(i, value)` stores one
+// population; 16-bit storage subtracts w_i ref here.
+template <typename C, typename Put>
+__device__ __forceinline__ void collide_component(const CompState<C> &st, C ux, C uy, C uz, C r2, C keep, C guo,
+                                                  C pe0, const C (&podd)[9], const C (&peven)[9], Put &&put) {
+    constexpr C T0 = C(1.0 / 3.0);
+    const Moments<C> &m = *st.m;
+    const C rho = st.rho, Fx = st.Fx, Fy = st.Fy, Fz = st.Fz;
+    // X: the non-equilibrium flux of Eq. (10) relaxed by 1 - 1/tau, plus the
+    // second-order forcing part.
+    const C rt = rho * T0, ru = r2 * rho;
+    const C g2 = C(2) * guo;
+    const C Xxx = keep * (m.xx - rt - ru * ux * ux) + g2 * ux * Fx;
+    const C Xyy = keep * (m.yy - rt - ru * uy * uy) + g2 * uy * Fy;
+    const C Xzz = keep * (m.zz - rt - ru * uz * uz) + g2 * uz * Fz;
+    const C Xxy = keep * (m.xy - ru * ux * uy) + guo * (ux * Fy + Fx * uy);
+    const C Xxz = keep * (m.xz - ru * ux * uz) + guo * (ux * Fz + Fx * uz);
+    const C Xyz = keep * (m.yz - ru * uy * uz) + guo * (uy * Fz + Fy * uz);
+    const C tr = Xxx + Xyy + Xzz;
+    const C t = T0 * tr;
+    const C ref = st.ref;
+
+    // rest population: w_0 = 1/3, c = 0
+    put(0, C(1.0 / 3.0) * (rho * pe0 - ref) - C(0.5) * tr);
+
+    // axis pairs (w = 1/18): 4.5 w (X_aa - t) - w ref and 1.5 w F_a
+    const C ref18 = ref * C(1.0 / 18.0), ref36 = ref * C(1.0 / 36.0);
+    const C Ax = C(0.25) * (Xxx - t) - ref18, Ay = C(0.25) * (Xyy - t) - ref18, Az = C(0.25) * (Xzz - t) - ref18;
+    // diagonal pairs (w = 1/36): 4.5 w (X_aa + X_bb - t) - w ref and 4.5 w 2 X_ab
+    const C Dxy = C(0.125) * (Xxx + Xyy - t) - ref36, Dxz = C(0.125) * (Xxx + Xzz - t) - ref36,
+            Dyz = C(0.125) * (Xyy + Xzz - t) - ref36;
+    const C Qxy = C(0.25) * Xxy, Qxz = C(0.25) * Xxz, Qyz = C(0.25) * Xyz;
+    const C F18x = Fx * C(1.0 / 12.0), F18y = Fy * C(1.0 / 12.0), F18z = Fz * C(1.0 / 12.0);
+    const C F36x = Fx * C(1.0 / 24.0), F36y = Fy * C(1.0 / 24.0), F36z = Fz * C(1.0 / 24.0);
+    const C r18 = rho * C(1.0 / 18.0), r36 = rho * C(1.0 / 36.0);
+
+    sfor<9>([&](auto K) {
+        constexpr int k = K;
+        constexpr int i = 2 * k + 1;
+        constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+        C ew, ow;   // w E and w O
+        if constexpr (i <= 6) {
+            const C A = X != 0 ? Ax : (Y != 0 ? Ay : Az);
+            const C Fa = X != 0 ? F18x : (Y != 0 ? F18y : F18z);
+            ew = r18 * peven[k] + A;
+            ow = r18 * podd[k] + Fa;   // c_a = +1 for the odd member
+        } else {
+            const C D = (X != 0 && Y != 0) ? Dxy : (X != 0 ? Dxz : Dyz);
+            const C Q = (X != 0 && Y != 0) ? Qxy : (X != 0 ? Qxz : Qyz);
+            constexpr int sg = X * Y + X * Z + Y * Z;   // product of the two non-zero components
+            ew = r36 * peven[k] + (sg > 0 ? D + Q : D - Q);
+            ow = r36 * podd[k] + dot_signed<X, Y, Z>(F36x, F36y, F36z);
+        }
+        put(i, ew + ow);
+        put(i + 1, ew - ow);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -293,6 +411,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
     const uint32_t nxyB = nxy * ESZ;
+    const uint32_t pb = a.plane_bytes;
 
     // This thread's ring site, in LDS coordinates (rr, rc).
     int rr, rc;
@@ -305,6 +424,8 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
 
     const Column ci = make_column(gx % nx, gy % ny, nx, ny, ESZ);
     const Column cr = make_column(wrap(tx * TX - 1 + rc, nx), wrap(ty * TY - 1 + rr, ny), nx, ny, ESZ);
+
+    const __amdgpu_buffer_rsrc_t src0 = component_rsrc(a.src, 0, pb), src1 = component_rsrc(a.src, 1, pb);
 
     Moments<C> mc[2], mn[2];     // moments of the plane to collide / of the next plane
     bool fluid_c = false, fluid_n = false;
@@ -324,33 +445,42 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
         const bool fi = !(Li & 1u), fr = !(Lr & 1u);
         S ri[2][19], rg[2][19];
         // All of the plane's loads are issued before any is consumed: one
-        // memory round trip per plane.  Waves without ring sites skip the
-        // ring issue (a uniform branch).
-        issue_pull<S>(a, ci, sz, Li, fi, ri);
-        if (ring_wave) issue_pull<S>(a, cr, sz, Lr, fr, rg);
+        // memory round trip per plane.  Lanes without a pull (solid sites,
+        // no ring site) issue no load and use none of these values.
+        if (fi) issue_pull<S, true>(src0, src1, ci, sz, pb, Li, ri);
+        if (has_ring && fr) issue_pull<S, true>(src0, src1, cr, sz, pb, Lr, rg);
         __builtin_amdgcn_sched_barrier(0);
-        C r0, r1;
-        if (keep) {
-            mn[0] = moments_of<S>(ri[0], ref0);
-            mn[1] = moments_of<S>(ri[1], ref1);
-            r0 = mn[0].r;
-            r1 = mn[1].r;
-        } else {
-            r0 = density_of<S>(ri[0], ref0);
-            r1 = density_of<S>(ri[1], ref1);
-        }
-        if (!fi) {
-            r0 = a.wall0;
-            r1 = a.wall1;
+        C r0 = a.wall0, r1 = a.wall1;
+        if (fi) {
+            if (keep) {
+                mn[0] = moments_of<S>(ri[0], ref0);
+                mn[1] = moments_of<S>(ri[1], ref1);
+                r0 = mn[0].r;
+                r1 = mn[1].r;
+            } else {
+                r0 = density_of<S>(ri[0], ref0);
+                r1 = density_of<S>(ri[1], ref1);
+            }
+        } else if (keep) {
+            // A solid site collides a harmless stand-in state so that the
+            // stores of every plane row cover whole cache lines (its values
+            // are never read: a pull from a solid site takes the bounce-back).
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                mn[d].r = C(0.5);
+                mn[d].jx = mn[d].jy = mn[d].jz = C(0);
+                mn[d].xx = mn[d].yy = mn[d].zz = C(0.5) * T0;
+                mn[d].xy = mn[d].xz = mn[d].yz = C(0);
+            }
         }
         fluid_n = fi;
         psi0[lslot][ly + 1][lx + 1] = r0;
         psi1[lslot][ly + 1][lx + 1] = r1;
         if (ring_wave) {
-            C q0 = density_of<S>(rg[0], ref0), q1 = density_of<S>(rg[1], ref1);
-            if (!fr) {
-                q0 = a.wall0;
-                q1 = a.wall1;
+            C q0 = a.wall0, q1 = a.wall1;
+            if (has_ring && fr) {
+                q0 = density_of<S>(rg[0], ref0);
+                q1 = density_of<S>(rg[1], ref1);
             }
             if (has_ring) {
                 psi0[lslot][rr][rc] = q0;
@@ -369,53 +499,44 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     mc[1] = mn[1];
     fluid_c = fluid_n;
 
+    const __amdgpu_buffer_rsrc_t dst0 = component_rsrc(a.dst, 0, pb), dst1 = component_rsrc(a.dst, 1, pb);
+
     for (int z = z0; z < z1; ++z) {
         const int sm = (z - z0) & 3, s0 = (z - z0 + 1) & 3, sp = (z - z0 + 2) & 3;
         load_plane(zwrap(z + 1), sp, true, zwrap(z + 2));
         __syncthreads();
 
         if (inside) {
-            // A solid site collides a harmless stand-in state so that the
-            // stores of every plane row cover whole cache lines (its values
-            // are never read: a pull from a solid site takes the bounce-back).
-            if (!fluid_c) {
-#pragma unroll
-                for (int d = 0; d < 2; ++d) {
-                    mc[d].r = C(0.5);
-                    mc[d].jx = mc[d].jy = mc[d].jz = C(0);
-                    mc[d].xx = mc[d].yy = mc[d].zz = C(0.5) * T0;
-                    mc[d].xy = mc[d].xz = mc[d].yz = C(0);
-                }
-            }
             const C rho[2] = {mc[0].r, mc[1].r};
 
             // Eqs. (7), (11): sum_i w_i c_i psi'(x + c_i) from the LDS planes.
-            C n0x = 0, n0y = 0, n0z = 0, n1x = 0, n1y = 0, n1z = 0;
+            const C nz0 = C(-0.0);
+            C n0x = nz0, n0y = nz0, n0z = nz0, n1x = nz0, n1y = nz0, n1z = nz0;
             sfor<19>([&](auto I) {
                 constexpr int i = I;
                 if constexpr (i > 0) {
                     constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
-                    constexpr C w = C(w_of(i));
+                    constexpr C wx = C(X * w_of(i)), wy = C(Y * w_of(i)), wz = C(Z * w_of(i));
                     const int sl = Z == 0 ? s0 : (Z > 0 ? sp : sm);
                     const C p0 = psi0[sl][ly + 1 + Y][lx + 1 + X];
                     const C p1 = psi1[sl][ly + 1 + Y][lx + 1 + X];
-                    if constexpr (X != 0) { n0x += C(X) * w * p0; n1x += C(X) * w * p1; }
-                    if constexpr (Y != 0) { n0y += C(Y) * w * p0; n1y += C(Y) * w * p1; }
-                    if constexpr (Z != 0) { n0z += C(Z) * w * p0; n1z += C(Z) * w * p1; }
+                    if constexpr (X != 0) { n0x += wx * p0; n1x += wx * p1; }
+                    if constexpr (Y != 0) { n0y += wy * p0; n1y += wy * p1; }
+                    if constexpr (Z != 0) { n0z += wz * p0; n1z += wz * p1; }
                 }
             });
             // Force on component 0 from component 1 and vice versa, plus body force.
             C Fx[2], Fy[2], Fz[2];
-            Fx[0] = a.G * rho[0] * n1x + rho[0] * a.gx;
-            Fy[0] = a.G * rho[0] * n1y + rho[0] * a.gy;
-            Fz[0] = a.G * rho[0] * n1z + rho[0] * a.gz;
-            Fx[1] = a.G * rho[1] * n0x + rho[1] * a.gx;
-            Fy[1] = a.G * rho[1] * n0y + rho[1] * a.gy;
-            Fz[1] = a.G * rho[1] * n0z + rho[1] * a.gz;
+            Fx[0] = rho[0] * (a.G * n1x + a.gx);
+            Fy[0] = rho[0] * (a.G * n1y + a.gy);
+            Fz[0] = rho[0] * (a.G * n1z + a.gz);
+            Fx[1] = rho[1] * (a.G * n0x + a.gx);
+            Fy[1] = rho[1] * (a.G * n0y + a.gy);
+            Fz[1] = rho[1] * (a.G * n0z + a.gz);
 
             // Eq. (8): u_F = (j_1 + j_2 + F / 2) / rho.
             const C rho_t = rho[0] + rho[1];
-            const C inv = C(1) / rho_t;
+            const C inv = recip(rho_t);
             const C ux = (mc[0].jx + mc[1].jx + C(0.5) * (Fx[0] + Fx[1])) * inv;
             const C uy = (mc[0].jy + mc[1].jy + C(0.5) * (Fy[0] + Fy[1])) * inv;
             const C uz = (mc[0].jz + mc[1].jz + C(0.5) * (Fz[0] + Fz[1])) * inv;
@@ -442,62 +563,33 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
             }
 
             if constexpr (MODE == MODE_STEP || MODE == MODE_CHECK) {
-                // Eqs. (5)-(6) with p = rho_1 / rho: tau_mix is linear in p.
-                const C tau = (rho[0] * a.tau0 + rho[1] * a.tau1) * inv;
-                const C omega = C(1) / tau;
+                // Eqs. (5)-(6) with p = rho_1 / rho: tau_mix is linear in p,
+                // so 1/tau = rho / (rho_1 tau_1 + rho_2 tau_2).
+                const C omega = rho_t * recip(rho[0] * a.tau0 + rho[1] * a.tau1);
                 const C keep = C(1) - omega;
                 const C guo = a.force_kind == 0 ? C(1) - C(0.5) * omega : C(0);
+
+                // The even and odd parts of P_i per opposite pair, shared by
+                // the two components.
                 const C r2 = a.eq_kind == 1 ? C(1) : C(0);
-
-                // Per component: X = (1 - 1/tau) Pi_neq + guo (u_F F + F u_F),
-                // projected by Phi of Eq. (10) into 4.5 w_i (c_i c_i - T0 I) : X.
-                C Xxx[2], Xyy[2], Xzz[2], Xxy[2], Xxz[2], Xyz[2], trX[2];
-#pragma unroll
-                for (int d = 0; d < 2; ++d) {
-                    const C rt = rho[d] * T0;
-                    const C ru = r2 * rho[d];
-                    Xxx[d] = keep * (mc[d].xx - rt - ru * ux * ux) + guo * C(2) * ux * Fx[d];
-                    Xyy[d] = keep * (mc[d].yy - rt - ru * uy * uy) + guo * C(2) * uy * Fy[d];
-                    Xzz[d] = keep * (mc[d].zz - rt - ru * uz * uz) + guo * C(2) * uz * Fz[d];
-                    Xxy[d] = keep * (mc[d].xy - ru * ux * uy) + guo * (ux * Fy[d] + Fx[d] * uy);
-                    Xxz[d] = keep * (mc[d].xz - ru * ux * uz) + guo * (ux * Fz[d] + Fx[d] * uz);
-                    Xyz[d] = keep * (mc[d].yz - ru * uy * uz) + guo * (uy * Fz[d] + Fy[d] * uz);
-                    trX[d] = Xxx[d] + Xyy[d] + Xzz[d];
-                }
-
-                // Eqs. (3), (9): f* = w_i [rho P_i + 4.5 (cc:X - T0 tr X) + 1.5 c.F],
-                // P_i = 1 + 3 cu + 4.5 cu^3 - 4.5 cu u^2 (+ 4.5 cu^2 - 1.5 u^2 with eq_kind 1);
-                // split into the parts even and odd under c -> -c.
-                char *dbase = reinterpret_cast<char *>(a.dst);
-                const uint32_t pb = a.plane_bytes;
-                const uint32_t sofs = ci.xy[4] + (uint32_t)z * nxyB;
-                auto put = [&](int d, int i, C v) {
-                    if constexpr (Codec<S>::shifted) v -= C(w_of(i)) * (d == 0 ? ref0 : ref1);
-                    stream_store<S>(reinterpret_cast<S *>(dbase + (size_t)(d * 19 + i) * pb + sofs), Codec<S>::st(v));
-                };
-#pragma unroll
-                for (int d = 0; d < 2; ++d)
-                    put(d, 0, C(1.0 / 3.0) * (rho[d] * (C(1) - r2 * C(1.5) * usq) - C(1.5) * trX[d]));
-                sfor<19>([&](auto I) {
-                    constexpr int i = I;
-                    if constexpr (i > 0 && (i & 1)) {
-                        constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
-                        constexpr C w = C(w_of(i));
-                        const C cu = C(X) * ux + C(Y) * uy + C(Z) * uz;
-                        const C even_c = C(1) + r2 * (C(4.5) * cu * cu - C(1.5) * usq);
-                        const C odd_c = cu * (C(3) + C(4.5) * (cu * cu - usq));
-#pragma unroll
-                        for (int d = 0; d < 2; ++d) {
-                            const C ccX = C(X * X) * Xxx[d] + C(Y * Y) * Xyy[d] + C(Z * Z) * Xzz[d] +
-                                          C(2 * X * Y) * Xxy[d] + C(2 * X * Z) * Xxz[d] + C(2 * Y * Z) * Xyz[d];
-                            const C cF = C(X) * Fx[d] + C(Y) * Fy[d] + C(Z) * Fz[d];
-                            const C E = rho[d] * even_c + C(4.5) * (ccX - T0 * trX[d]);
-                            const C O = rho[d] * odd_c + C(1.5) * cF;
-                            put(d, i, w * (E + O));
-                            put(d, i + 1, w * (E - O));
-                        }
-                    }
+                const C pe0 = C(1) - r2 * C(1.5) * usq;
+                C podd[9], peven[9];
+                sfor<9>([&](auto K) {
+                    constexpr int i = 2 * K + 1;
+                    const C cu = dot_signed<cx_of(i), cy_of(i), cz_of(i)>(ux, uy, uz);
+                    podd[K] = cu * (C(3) + C(4.5) * (cu * cu - usq));
+                    peven[K] = pe0 + r2 * C(4.5) * cu * cu;
                 });
+
+                const uint32_t vo = ci.xy[4];
+                const uint32_t zo = (uint32_t)z * nxyB;
+                auto put0 = [&](int i, C v) { buf_store<S>(Codec<S>::st(v), dst0, vo, zo + (uint32_t)i * pb); };
+                auto put1 = [&](int i, C v) { buf_store<S>(Codec<S>::st(v), dst1, vo, zo + (uint32_t)i * pb); };
+                const C sref0 = Codec<S>::shifted ? ref0 : C(0), sref1 = Codec<S>::shifted ? ref1 : C(0);
+                const CompState<C> st0{rho[0], Fx[0], Fy[0], Fz[0], &mc[0], sref0};
+                const CompState<C> st1{rho[1], Fx[1], Fy[1], Fz[1], &mc[1], sref1};
+                collide_component(st0, ux, uy, uz, r2, keep, guo, pe0, podd, peven, put0);
+                collide_component(st1, ux, uy, uz, r2, keep, guo, pe0, podd, peven, put1);
             }
         }
 
