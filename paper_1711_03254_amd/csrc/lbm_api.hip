@@ -20,7 +20,8 @@ struct lbm_ctx {
     size_t esz = 0;
     void *f[2] = {nullptr, nullptr};
     int cur = 0;
-    uint32_t *links = nullptr;
+    uint32_t *links = nullptr;   // per-site link mask (set-up and exchange kernels)
+    int32_t *idx = nullptr;      // compact population index per site, -1 where solid
     double *partials = nullptr;
     double *red_dev = nullptr;
     double *red_host = nullptr;   // pinned
@@ -131,7 +132,7 @@ lbm::StepLaunch make_launch(const lbm_ctx *c, const void *src, void *dst) {
     lbm::StepLaunch L{};
     L.src = src;
     L.dst = dst;
-    L.links = c->links;
+    L.idx = c->idx;
     L.nx = p.nx; L.ny = p.ny; L.nz = p.nz;
     L.plane = c->plane;
     L.tile_x = c->tile_x; L.tile_y = c->tile_y; L.zchunk = c->zchunk;
@@ -240,7 +241,7 @@ int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u,
     HIPCHK(c, hipMemcpyAsync(c->stage, vr0, NB, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->stage + c->N, vr1, NB, hipMemcpyHostToDevice, c->stream));
     if (vu) HIPCHK(c, hipMemcpyAsync(c->stage + 2 * c->N, vu, 3 * NB, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, lbm::launch_init_fields(c->p.prec, c->f[c->cur], c->links, c->stage, c->stage + c->N,
+    HIPCHK(c, lbm::launch_init_fields(c->p.prec, c->f[c->cur], c->links, c->idx, c->stage, c->stage + c->N,
                                       vu ? c->stage + 2 * c->N : nullptr, c->p.nx, c->p.ny, c->p.nz, c->plane,
                                       c->p.eq_kind, c->ref, c->stream));
     rc = measure(c, nullptr, nullptr, nullptr);
@@ -250,11 +251,31 @@ int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u,
     return LBM_OK;
 }
 
+// Compact index of the fluid sites: tile column by tile column (the step's
+// x-y tiles), z plane by plane, row by row within a tile, so that the sites
+// one block updates are contiguous in every population plane.
+int64_t build_index(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty, std::vector<int32_t> &idx) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    idx.assign((size_t)N, -1);
+    int64_t k = 0;
+    const int ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty;
+    for (int by = 0; by < nty; ++by)
+        for (int bx = 0; bx < ntx; ++bx)
+            for (int z = 0; z < nz; ++z)
+                for (int y = by * ty; y < std::min(ny, (by + 1) * ty); ++y)
+                    for (int x = bx * tx; x < std::min(nx, (bx + 1) * tx); ++x) {
+                        const int64_t s = x + (int64_t)nx * (y + (int64_t)ny * z);
+                        if (!solid || !solid[s]) idx[(size_t)s] = (int32_t)k++;
+                    }
+    return k;
+}
+
 void release(lbm_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (void *q : {c->f[0], c->f[1], (void *)c->links, (void *)c->partials, (void *)c->red_dev, (void *)c->stage})
+    for (void *q : {c->f[0], c->f[1], (void *)c->links, (void *)c->idx, (void *)c->partials, (void *)c->red_dev,
+                    (void *)c->stage})
         if (q) (void)hipFree(q);
     if (c->red_host) (void)hipHostFree(c->red_host);
     for (int k = 0; k < 2; ++k) {
@@ -302,12 +323,10 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
     if (c->p.mass_tol == 0) c->p.mass_tol = default_mass_tol(p.prec);
     c->N = (int64_t)p.nx * p.ny * p.nz;
     c->esz = esz;
-    // Each plane starts 256-byte aligned; the odd padding keeps the 38 planes
-    // of a buffer from starting at the same offsets modulo large powers of two.
-    c->plane = (c->N + 127) / 128 * 128 + 128 * 13;
-    // The step addresses a component's 19 planes with 32-bit byte offsets.
-    if (19 * (uint64_t)c->plane * esz >= (1ull << 32)) {
-        int rc = fail(nullptr, LBM_EINVAL, "lattice too large: the 19 planes of one component must stay below 4 GiB");
+    // Site indices are 32-bit (and the index map is read through a buffer
+    // resource of 4 N bytes).
+    if (c->N >= (int64_t)1 << 30) {
+        int rc = fail(nullptr, LBM_EINVAL, "lattice too large: at most 2^30 sites");
         delete c;
         return rc;
     }
@@ -325,6 +344,25 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
             return bail(fail(c, LBM_EDEVICE, "hipStreamCreate failed"));
         c->own_stream = true;
     }
+
+    // Solid mask on the host, the compact index of the fluid sites.
+    std::vector<uint8_t> solid_h;
+    if (p.solid) {
+        solid_h.resize((size_t)c->N);
+        if (!p.inputs_on_device) std::memcpy(solid_h.data(), p.solid, (size_t)c->N);
+        else if (hipMemcpy(solid_h.data(), p.solid, c->N, hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(fail(c, LBM_EDEVICE, "cannot read the solid mask"));
+    }
+    std::vector<int32_t> idx_h;
+    const int64_t nfl = build_index(p.solid ? solid_h.data() : nullptr, p.nx, p.ny, p.nz, c->tile_x, c->tile_y, idx_h);
+    if (nfl == 0) return bail(fail(c, LBM_EINVAL, "the lattice has no fluid site"));
+    // Each plane starts 256-byte aligned; the odd padding keeps the 38 planes
+    // of a buffer from starting at the same offsets modulo large powers of two.
+    c->plane = (nfl + 127) / 128 * 128 + 128 * 13;
+    // The step addresses a component's 19 planes with 32-bit byte offsets.
+    if (19 * (uint64_t)c->plane * esz >= (1ull << 32))
+        return bail(fail(c, LBM_EINVAL, "lattice too large: the 19 planes of one component must stay below 4 GiB"));
+
     const size_t fbytes = (size_t)2 * 19 * c->plane * esz;
     for (int k = 0; k < 2; ++k) {
         if (hipMalloc(&c->f[k], fbytes) != hipSuccess) {
@@ -335,17 +373,19 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
             return bail(fail(c, LBM_EDEVICE, "hipMemset failed"));
     }
     if (hipMalloc(&c->links, sizeof(uint32_t) * c->N) != hipSuccess ||
+        hipMalloc(&c->idx, sizeof(int32_t) * c->N) != hipSuccess ||
         hipMalloc(&c->partials, sizeof(double) * lbm::kPartialStride * nblocks(c)) != hipSuccess ||
         hipMalloc(&c->red_dev, sizeof(double) * lbm::kPartialStride) != hipSuccess ||
         hipHostMalloc(&c->red_host, sizeof(double) * lbm::kPartialStride, hipHostMallocDefault) != hipSuccess)
-        return bail(fail(c, LBM_ENOMEM, "cannot allocate the link mask or reduction buffers"));
+        return bail(fail(c, LBM_ENOMEM, "cannot allocate the link mask, index or reduction buffers"));
+    if (hipMemcpy(c->idx, idx_h.data(), sizeof(int32_t) * c->N, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(c, LBM_EDEVICE, "cannot upload the site index"));
 
     // Solid mask -> link mask.
     uint8_t *solid_d = nullptr;
     if (p.solid) {
         if (hipMalloc(&solid_d, c->N) != hipSuccess) return bail(fail(c, LBM_ENOMEM, "cannot stage the solid mask"));
-        hipError_t e = hipMemcpyAsync(solid_d, p.solid, c->N,
-                                      p.inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+        hipError_t e = hipMemcpyAsync(solid_d, solid_h.data(), c->N, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = lbm::launch_links(solid_d, c->links, p.nx, p.ny, p.nz, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         (void)hipFree(solid_d);
@@ -504,7 +544,7 @@ int lbm_get_populations(lbm_ctx *c, double *f, int on_device) {
         (void)hipGetLastError();
         return fail(c, LBM_ENOMEM, "cannot allocate the population staging buffer");
     }
-    hipError_t e = lbm::launch_get_pops(c->p.prec, c->f[c->cur], c->links, dst, c->p.nx, c->p.ny, c->p.nz, c->plane,
+    hipError_t e = lbm::launch_get_pops(c->p.prec, c->f[c->cur], c->links, c->idx, dst, c->p.nx, c->p.ny, c->p.nz, c->plane,
                                         c->ref, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess && !on_device) e = hipMemcpy(f, dst, bytes, hipMemcpyDeviceToHost);
@@ -528,7 +568,7 @@ int lbm_set_populations(lbm_ctx *c, const double *f, int on_device) {
             return fail(c, LBM_EDEVICE, "set_populations: copy failed");
         }
     }
-    hipError_t e = lbm::launch_set_pops(c->p.prec, c->f[c->cur], c->links, src, c->p.nx, c->p.ny, c->p.nz, c->plane,
+    hipError_t e = lbm::launch_set_pops(c->p.prec, c->f[c->cur], c->links, c->idx, src, c->p.nx, c->p.ny, c->p.nz, c->plane,
                                         c->ref, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (!on_device) (void)hipFree(src);

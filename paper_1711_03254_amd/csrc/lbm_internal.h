@@ -28,9 +28,9 @@ constexpr int kPartialStride = 8;
 struct StepLaunch {
     const void *src;
     void *dst;
-    const uint32_t *links;
+    const int32_t *idx;     // compact population index of each lattice site, -1 where solid
     int nx, ny, nz;
-    int64_t plane;          // elements per (component, direction) plane
+    int64_t plane;          // elements per (component, direction) plane (fluid sites plus padding)
     int tile_x, tile_y, zchunk;
     int ntx, nty, nzc;      // tiles in x, y and chunks in z
     double tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
@@ -46,17 +46,17 @@ hipError_t launch_finalize(const double *partials, int nblocks, double *out, hip
 // Per-site link mask: bit 0 = site solid, bit i = site - c_i solid (periodic).
 hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, int nz, hipStream_t s);
 // Internal state from fields: f*_j(x) = f_eq,j(x + c_j) if that site is fluid,
-// else f_eq,opp(j)(x); f_eq from rho (2N), u (3N or null).
-hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const double *rho0,
-                              const double *rho1, const double *u, int nx, int ny, int nz,
-                              int64_t plane, int eq_kind, const double ref[2], hipStream_t s);
+// else f_eq,opp(j)(x); f_eq from rho (2N), u (3N or null).  Populations of
+// fluid site s are at compact index idx[s] of each plane.
+hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
+                              const double *rho1, const double *u, int nx, int ny, int nz, int64_t plane,
+                              int eq_kind, const double ref[2], hipStream_t s);
 // Internal state from ABI populations (inverse of the pull).
-hipError_t launch_set_pops(int prec, void *dst, const uint32_t *links, const double *f, int nx,
+hipError_t launch_set_pops(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *f, int nx,
                            int ny, int nz, int64_t plane, const double ref[2], hipStream_t s);
-// ABI populations from the internal state (the pull).
-hipError_t launch_get_pops(int prec, const void *src, const uint32_t *links, double *f, int nx,
+// ABI populations from the internal state (the pull); solid sites read 0.
+hipError_t launch_get_pops(int prec, const void *src, const uint32_t *links, const int32_t *idx, double *f, int nx,
                            int ny, int nz, int64_t plane, const double ref[2], hipStream_t s);
-
 // Batched launches over many domains: a descriptor per domain (the typed
 // kernel arguments, built by fill_batch_desc from a StepLaunch) and a work list
 // of (domain, tile) pairs; flip swaps each descriptor's (src, dst).

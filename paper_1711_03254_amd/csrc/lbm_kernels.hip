@@ -1,10 +1,13 @@
 // lbm_kernels.hip -- gfx950 kernels of the two-component Shan-Chen D3Q19 step
 // (Otomo et al., arXiv:1711.03254, Section 2, Eqs. 1-11).
 //
-// Storage: per (component, direction) plane a contiguous array of N sites,
-// x fastest.  The buffer a step reads holds the post-collision populations
-// f*(x, t-1) of the previous step; the step pulls f_i(x, t) = f*_i(x - c_i)
-// (or, when x - c_i is solid, the reversed population f*_opp(i)(x): halfway
+// Storage: populations exist for fluid sites only.  Each fluid site has a
+// compact index k (the host numbers them tile column by tile column, z
+// plane by plane, so that a block's sites are contiguous); per
+// (component, direction) plane the populations are an array over k.  The
+// buffer a step reads holds the post-collision populations f*(x, t-1) of
+// the previous step; the step pulls f_i(x, t) = f*_i(x - c_i) (or, when
+// x - c_i is solid, the reversed population f*_opp(i)(x): halfway
 // bounce-back), collides and writes f*(x, t) at x into the other buffer.
 //
 // The Shan-Chen force at x needs the densities of the 18 neighbours at time
@@ -12,8 +15,10 @@
 // x-y tile of TX x TY columns and marches along z through a chunk of planes;
 // for every plane it pulls the tile and its one-site ring, sums the
 // densities into an LDS ring buffer of four planes, and collides the plane
-// behind once the plane ahead is known.  The ring's pulls are the only
-// redundant work (loads that mostly hit L2); no density array goes to HBM.
+// behind once the plane ahead is known.  The compact indices of the tile
+// and a ring of two sites are staged in LDS too (five planes), so each pull
+// finds its 18 sources (or the wall) there.  The ring's pulls are the only
+// redundant work; no density array goes to HBM.
 
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
@@ -89,7 +94,7 @@ struct KArgs {
     using C = typename Codec<S>::C;
     const S *src;
     S *dst;
-    const uint32_t *links;
+    const int32_t *idx;     // compact index of each lattice site, -1 where solid
     int nx, ny, nz, ntx, nty, zchunk;
     uint32_t plane_bytes;   // bytes of one (component, direction) plane
     C tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
@@ -102,35 +107,6 @@ struct KArgs {
 __device__ __forceinline__ int wrap(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
-}
-
-// Byte offsets of the source sites (x - cx, y - cy) for cx, cy in {-1,0,1},
-// index (cy + 1) * 3 + (cx + 1), of one column.
-struct Column {
-    uint32_t xy[9];
-    uint32_t site;   // x + nx y (element index)
-};
-
-__device__ __forceinline__ Column make_column(int x, int y, int nx, int ny, uint32_t esz) {
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-    const int sx[3] = {xp, x, xm};           // source x of cx = -1, 0, +1
-    const int sy[3] = {yp * nx, y * nx, ym * nx};
-    Column c;
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) c.xy[j * 3 + k] = (uint32_t)(sx[k] + sy[j]) * esz;
-    c.site = (uint32_t)(x + y * nx);
-    return c;
-}
-
-// Byte offsets of the source planes z - cz for cz = -1, 0, +1.
-__device__ __forceinline__ void plane_offsets(int z, int nz, uint32_t nxy_bytes, uint32_t (&sz)[3]) {
-    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-    sz[0] = (uint32_t)zp * nxy_bytes;
-    sz[1] = (uint32_t)z * nxy_bytes;
-    sz[2] = (uint32_t)zm * nxy_bytes;
 }
 
 // Raw buffer access.  One buffer resource spans the 19 planes of one
@@ -172,40 +148,6 @@ template <typename S> __device__ __forceinline__ void buf_store(S x, __amdgpu_bu
     } else {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, kNonTemporal);
     }
-}
-
-// Pull of one site: f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) when link bit i
-// says x - c_i is solid (halfway bounce-back).  Both members of an opposite
-// pair (odd i, i + 1) are addressed from the odd member's plane, the scalar
-// offset, so the bounce-back is a select between two lane offsets.  WALLS =
-// false is the form for waves without any solid link.  Only issues the
-// loads: a plane's interior and ring loads are all in flight before any is
-// consumed.
-template <typename S, bool WALLS>
-__device__ __forceinline__ void issue_pull(__amdgpu_buffer_rsrc_t r0, __amdgpu_buffer_rsrc_t r1, const Column &col,
-                                           const uint32_t (&sz)[3], uint32_t pb, uint32_t L, S (&raw)[2][19]) {
-    const uint32_t self = col.xy[4] + sz[1];
-    const uint32_t self_p = self + pb;
-    sfor<19>([&](auto I) {
-        constexpr int i = I;
-        constexpr int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-        const uint32_t soff = (uint32_t)lo * pb;
-        uint32_t off;
-        if constexpr (i == 0) {
-            off = self;
-        } else {
-            const uint32_t stream =
-                col.xy[(cy_of(i) + 1) * 3 + cx_of(i) + 1] + (sz[cz_of(i) + 1] + (i == lo ? 0u : pb));
-            if constexpr (WALLS) {
-                const bool wall = (L >> i) & 1u;
-                off = wall ? (i == lo ? self_p : self) : stream;
-            } else {
-                off = stream;
-            }
-        }
-        raw[0][i] = buf_load<S>(r0, off, soff);
-        raw[1][i] = buf_load<S>(r1, off, soff);
-    });
 }
 
 // Eq. (4) and the second moments of one component's pulled populations:
@@ -387,14 +329,17 @@ template <typename S, int TX, int TY, int MODE>
 __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     using C = typename Codec<S>::C;
     constexpr int NT = TX * TY;
-    constexpr int RW = TX + 2, RH = TY + 2;
-    constexpr int NR = 2 * RW + 2 * TY;       // ring sites of the tile
+    constexpr int RW = TX + 2, RH = TY + 2;     // density tile with its ring
+    constexpr int HW = TX + 4, HH = TY + 4;     // index tile with a ring of two
+    constexpr int NE = (HW * HH + NT - 1) / NT; // index-tile entries per thread
+    constexpr int NR = 2 * RW + 2 * TY;         // ring sites of the tile
     static_assert(NR <= NT, "the ring must fit in the block");
     constexpr uint32_t ESZ = sizeof(S);
-    constexpr C T0 = C(1.0 / 3.0);
 
     __shared__ C psi0[4][RH][RW];
     __shared__ C psi1[4][RH][RW];
+    // byte offset k * ESZ of each site's populations within a plane, -1 where solid
+    __shared__ int kid[5][HH][HW];
     __shared__ double red[NT / 64][6];
 
     const int tx = b % a.ntx;
@@ -410,45 +355,96 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     const bool inside = gx < a.nx && gy < a.ny;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
-    const uint32_t nxyB = nxy * ESZ;
     const uint32_t pb = a.plane_bytes;
+    const uint32_t site_xy = (uint32_t)(gx % nx) + (uint32_t)nx * (uint32_t)(gy % ny);
 
-    // This thread's ring site, in LDS coordinates (rr, rc).
-    int rr, rc;
+    // This thread's ring site, in density-tile coordinates (rr, rc).
+    const bool has_ring = tid < NR;
+    const bool ring_wave = (tid & ~63) < NR;   // the wave holds at least one ring site
+    int rr = 0, rc = 0;
     if (tid < RW) { rr = 0; rc = tid; }
     else if (tid < 2 * RW) { rr = RH - 1; rc = tid - RW; }
     else if (tid < 2 * RW + TY) { rr = 1 + tid - 2 * RW; rc = 0; }
-    else { rr = 1 + tid - 2 * RW - TY; rc = RW - 1; }
-    const bool has_ring = tid < NR;
-    const bool ring_wave = (tid & ~63) < NR;   // the wave holds at least one ring site
+    else if (tid < NR) { rr = 1 + tid - 2 * RW - TY; rc = RW - 1; }
 
-    const Column ci = make_column(gx % nx, gy % ny, nx, ny, ESZ);
-    const Column cr = make_column(wrap(tx * TX - 1 + rc, nx), wrap(ty * TY - 1 + rr, ny), nx, ny, ESZ);
+    // The index-tile entries this thread stages: their lattice (x, y).
+    uint32_t exy[NE];
+    bool eok[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        const int e = tid + j * NT;
+        eok[j] = e < HW * HH;
+        const int er = e / HW, ec = e % HW;
+        exy[j] = (uint32_t)wrap(tx * TX - 2 + ec, nx) + (uint32_t)nx * (uint32_t)wrap(ty * TY - 2 + er, ny);
+    }
+    const __amdgpu_buffer_rsrc_t ridx = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int32_t *>(a.idx), 0, (int)(4u * (uint32_t)a.n_sites), kRsrcWord3);
+    auto fetch_idx = [&](int zq, int (&v)[NE]) {
+        const uint32_t zo = (uint32_t)wrap(zq, nz) * nxy * 4u;
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+            v[j] = -1;
+            if (eok[j]) v[j] = (int)__builtin_amdgcn_raw_buffer_load_b32(ridx, exy[j] * 4u, zo, 0);
+        }
+    };
+    auto store_idx = [&](int q, const int (&v)[NE]) {
+#pragma unroll
+        for (int j = 0; j < NE; ++j)
+            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? v[j] * (int)ESZ : -1;
+    };
 
     const __amdgpu_buffer_rsrc_t src0 = component_rsrc(a.src, 0, pb), src1 = component_rsrc(a.src, 1, pb);
 
+    // Pull of the site at index-tile position (hr, hc) whose populations sit
+    // at byte offset self, planes zw - 1, zw, zw + 1 in index slots qm, q0,
+    // qp: f_i = f*_i(x - c_i), or f*_opp(i)(x) when x - c_i is solid.  Both
+    // members of an opposite pair are addressed from the odd member's plane
+    // (the scalar offset), so the bounce-back is a select of lane offsets.
+    auto issue = [&](int hr, int hc, int qm, int q0, int qp, uint32_t self, S (&raw)[2][19]) {
+        const uint32_t self_p = self + pb;
+        sfor<19>([&](auto I) {
+            constexpr int i = I;
+            constexpr int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+            const uint32_t soff = (uint32_t)lo * pb;
+            uint32_t off;
+            if constexpr (i == 0) {
+                off = self;
+            } else {
+                constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+                const int q = Z == 0 ? q0 : (Z > 0 ? qm : qp);   // plane zw - Z
+                const int nb = kid[q][hr - Y][hc - X];
+                if constexpr (i == lo) off = nb >= 0 ? (uint32_t)nb : self_p;
+                else off = nb >= 0 ? (uint32_t)nb + pb : self;
+            }
+            raw[0][i] = buf_load<S>(src0, off, soff);
+            raw[1][i] = buf_load<S>(src1, off, soff);
+        });
+    };
+
     Moments<C> mc[2], mn[2];     // moments of the plane to collide / of the next plane
+#pragma unroll
+    for (int d = 0; d < 2; ++d) mn[d] = Moments<C>{C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
     bool fluid_c = false, fluid_n = false;
+    int kc = 0, kn = 0;          // byte offsets of this site in the plane to collide / the next plane
     const C ref0 = a.ref0, ref1 = a.ref1;
 
-    // link words, fetched one plane ahead
-    auto zwrap = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
-    uint32_t Li = a.links[ci.site + (uint32_t)zwrap(z0 - 1) * nxy];
-    uint32_t Lr = has_ring ? a.links[cr.site + (uint32_t)zwrap(z0 - 1) * nxy] : 1u;
-
-    // Pulls plane zw into LDS slot `slot`; the interior's moments go to mn.
-    auto load_plane = [&](int zw, int lslot, bool keep, int zw_next) {
-        uint32_t sz[3];
-        plane_offsets(zw, nz, nxyB, sz);
-        const uint32_t Lin = a.links[ci.site + (uint32_t)zw_next * nxy];
-        const uint32_t Lrn = has_ring ? a.links[cr.site + (uint32_t)zw_next * nxy] : 1u;
-        const bool fi = !(Li & 1u), fr = !(Lr & 1u);
+    // Pulls plane zw (z0 - 1 <= zw <= z1, unwrapped) into density slot
+    // lslot; the interior's moments go to mn.  Index slot of plane p:
+    // (p - z0 + 2) mod 5; the tile of plane zw + 2 is staged on the way.
+    auto load_plane = [&](int zw, int lslot, bool keep) {
+        const int qw = zw - z0 + 2;
+        const int qm = (qw + 4) % 5, q0 = qw % 5, qp = (qw + 1) % 5;
+        const int si = kid[q0][ly + 2][lx + 2];
+        const int sr = has_ring ? kid[q0][rr + 1][rc + 1] : -1;
+        const bool fi = si >= 0, fr = sr >= 0;
+        int vnext[NE];
+        fetch_idx(zw + 2, vnext);
         S ri[2][19], rg[2][19];
         // All of the plane's loads are issued before any is consumed: one
         // memory round trip per plane.  Lanes without a pull (solid sites,
         // no ring site) issue no load and use none of these values.
-        if (fi) issue_pull<S, true>(src0, src1, ci, sz, pb, Li, ri);
-        if (has_ring && fr) issue_pull<S, true>(src0, src1, cr, sz, pb, Lr, rg);
+        if (fi) issue(ly + 2, lx + 2, qm, q0, qp, (uint32_t)si, ri);
+        if (fr) issue(rr + 1, rc + 1, qm, q0, qp, (uint32_t)sr, rg);
         __builtin_amdgcn_sched_barrier(0);
         C r0 = a.wall0, r1 = a.wall1;
         if (fi) {
@@ -461,52 +457,53 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                 r0 = density_of<S>(ri[0], ref0);
                 r1 = density_of<S>(ri[1], ref1);
             }
-        } else if (keep) {
-            // A solid site collides a harmless stand-in state so that the
-            // stores of every plane row cover whole cache lines (its values
-            // are never read: a pull from a solid site takes the bounce-back).
-#pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                mn[d].r = C(0.5);
-                mn[d].jx = mn[d].jy = mn[d].jz = C(0);
-                mn[d].xx = mn[d].yy = mn[d].zz = C(0.5) * T0;
-                mn[d].xy = mn[d].xz = mn[d].yz = C(0);
-            }
         }
         fluid_n = fi;
+        kn = si;
         psi0[lslot][ly + 1][lx + 1] = r0;
         psi1[lslot][ly + 1][lx + 1] = r1;
         if (ring_wave) {
-            C q0 = a.wall0, q1 = a.wall1;
-            if (has_ring && fr) {
-                q0 = density_of<S>(rg[0], ref0);
-                q1 = density_of<S>(rg[1], ref1);
+            C q0v = a.wall0, q1v = a.wall1;
+            if (fr) {
+                q0v = density_of<S>(rg[0], ref0);
+                q1v = density_of<S>(rg[1], ref1);
             }
             if (has_ring) {
-                psi0[lslot][rr][rc] = q0;
-                psi1[lslot][rr][rc] = q1;
+                psi0[lslot][rr][rc] = q0v;
+                psi1[lslot][rr][rc] = q1v;
             }
         }
-        Li = Lin;
-        Lr = Lrn;
+        store_idx((qw + 2) % 5, vnext);
     };
 
     double acc[6] = {0, 0, 0, 0, 0, 0};
 
-    load_plane(zwrap(z0 - 1), 0, false, z0);
-    load_plane(z0, 1, true, zwrap(z0 + 1));
+    {   // index tiles of planes z0 - 2, z0 - 1, z0
+        int v[NE];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            fetch_idx(z0 - 2 + q, v);
+            store_idx(q, v);
+        }
+    }
+    __syncthreads();
+    load_plane(z0 - 1, 0, false);
+    __syncthreads();
+    load_plane(z0, 1, true);
     mc[0] = mn[0];
     mc[1] = mn[1];
     fluid_c = fluid_n;
+    kc = kn;
+    __syncthreads();
 
     const __amdgpu_buffer_rsrc_t dst0 = component_rsrc(a.dst, 0, pb), dst1 = component_rsrc(a.dst, 1, pb);
 
     for (int z = z0; z < z1; ++z) {
         const int sm = (z - z0) & 3, s0 = (z - z0 + 1) & 3, sp = (z - z0 + 2) & 3;
-        load_plane(zwrap(z + 1), sp, true, zwrap(z + 2));
+        load_plane(z + 1, sp, true);
         __syncthreads();
 
-        if (inside) {
+        if (inside && fluid_c) {
             const C rho[2] = {mc[0].r, mc[1].r};
 
             // Eqs. (7), (11): sum_i w_i c_i psi'(x + c_i) from the LDS planes.
@@ -542,7 +539,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
             const C uz = (mc[0].jz + mc[1].jz + C(0.5) * (Fz[0] + Fz[1])) * inv;
             const C usq = ux * ux + uy * uy + uz * uz;
 
-            if constexpr (MODE == MODE_CHECK || MODE == MODE_MOMENTS) if (fluid_c) {
+            if constexpr (MODE == MODE_CHECK || MODE == MODE_MOMENTS) {
                 const bool ok = isfinite(rho[0]) && isfinite(rho[1]) && isfinite(ux) && isfinite(uy) && isfinite(uz);
                 acc[0] += (double)rho[0];
                 acc[1] += (double)rho[1];
@@ -551,8 +548,8 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                 acc[4] += (double)rho_t * (double)uz;
                 acc[5] += ok ? 0.0 : 1.0;
             }
-            if constexpr (MODE == MODE_MOMENTS) if (fluid_c) {
-                const uint32_t s = ci.site + (uint32_t)z * nxy;
+            if constexpr (MODE == MODE_MOMENTS) {
+                const uint32_t s = site_xy + (uint32_t)z * nxy;
                 if (a.out_rho0) a.out_rho0[s] = (double)rho[0];
                 if (a.out_rho1) a.out_rho1[s] = (double)rho[1];
                 if (a.out_u) {
@@ -581,10 +578,9 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                     peven[K] = pe0 + r2 * C(4.5) * cu * cu;
                 });
 
-                const uint32_t vo = ci.xy[4];
-                const uint32_t zo = (uint32_t)z * nxyB;
-                auto put0 = [&](int i, C v) { buf_store<S>(Codec<S>::st(v), dst0, vo, zo + (uint32_t)i * pb); };
-                auto put1 = [&](int i, C v) { buf_store<S>(Codec<S>::st(v), dst1, vo, zo + (uint32_t)i * pb); };
+                const uint32_t vo = (uint32_t)kc;
+                auto put0 = [&](int i, C v) { buf_store<S>(Codec<S>::st(v), dst0, vo, (uint32_t)i * pb); };
+                auto put1 = [&](int i, C v) { buf_store<S>(Codec<S>::st(v), dst1, vo, (uint32_t)i * pb); };
                 const C sref0 = Codec<S>::shifted ? ref0 : C(0), sref1 = Codec<S>::shifted ? ref1 : C(0);
                 const CompState<C> st0{rho[0], Fx[0], Fy[0], Fz[0], &mc[0], sref0};
                 const CompState<C> st1{rho[1], Fx[1], Fy[1], Fz[1], &mc[1], sref1};
@@ -596,6 +592,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
         mc[0] = mn[0];
         mc[1] = mn[1];
         fluid_c = fluid_n;
+        kc = kn;
     }
 
     if constexpr (MODE == MODE_CHECK || MODE == MODE_MOMENTS) {
@@ -708,26 +705,29 @@ __device__ __forceinline__ double feq_dir(int i, double rho, double ux, double u
 }
 
 template <typename S>
-__device__ __forceinline__ void store_pop(S *dst, int64_t plane, int d, int i, int64_t s, double v, double ref) {
+__device__ __forceinline__ void store_pop(S *dst, int64_t plane, int d, int i, int64_t k, double v, double ref) {
     if constexpr (Codec<S>::shifted) v -= w_of(i) * ref;
-    dst[(int64_t)(d * 19 + i) * plane + s] = Codec<S>::st((typename Codec<S>::C)v);
+    dst[(int64_t)(d * 19 + i) * plane + k] = Codec<S>::st((typename Codec<S>::C)v);
 }
 
 template <typename S>
-__device__ __forceinline__ double load_pop(const S *src, int64_t plane, int d, int i, int64_t s, double ref) {
-    double v = (double)Codec<S>::ld(src[(int64_t)(d * 19 + i) * plane + s]);
+__device__ __forceinline__ double load_pop(const S *src, int64_t plane, int d, int i, int64_t k, double ref) {
+    double v = (double)Codec<S>::ld(src[(int64_t)(d * 19 + i) * plane + k]);
     if constexpr (Codec<S>::shifted) v += w_of(i) * ref;
     return v;
 }
 
+// The set-up and exchange kernels address a fluid site s's populations by
+// its compact index idx[s] (solid sites have none).
 template <typename S>
-__global__ void init_fields_kernel(S *dst, const uint32_t *links, const double *rho0, const double *rho1,
-                                   const double *u, int nx, int ny, int nz, int64_t plane, int eq_kind,
-                                   double ref0, double ref1) {
+__global__ void init_fields_kernel(S *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
+                                   const double *rho1, const double *u, int nx, int ny, int nz, int64_t plane,
+                                   int eq_kind, double ref0, double ref1) {
     const int64_t N = (int64_t)nx * ny * nz;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t L = links[s];
         if (L & 1u) continue;
+        const int64_t k = idx[s];
         int x, y, z;
         site_coords(s, nx, ny, x, y, z);
         sfor<19>([&](auto I) {
@@ -735,41 +735,47 @@ __global__ void init_fields_kernel(S *dst, const uint32_t *links, const double *
             // f*_j(x) = f_j(x + c_j) if x + c_j is fluid, else f_opp(j)(x).
             const bool wall = j != 0 && ((L >> opp_of(j)) & 1u);
             const int64_t t = wall ? s : site_shift(x, y, z, cx_of(j), cy_of(j), cz_of(j), nx, ny, nz);
-            const int k = wall ? opp_of(j) : j;
+            const int kk = wall ? opp_of(j) : j;
             const double ux = u ? u[t] : 0.0, uy = u ? u[N + t] : 0.0, uz = u ? u[2 * N + t] : 0.0;
-            store_pop<S>(dst, plane, 0, j, s, feq_dir(k, rho0[t], ux, uy, uz, eq_kind), ref0);
-            store_pop<S>(dst, plane, 1, j, s, feq_dir(k, rho1[t], ux, uy, uz, eq_kind), ref1);
+            store_pop<S>(dst, plane, 0, j, k, feq_dir(kk, rho0[t], ux, uy, uz, eq_kind), ref0);
+            store_pop<S>(dst, plane, 1, j, k, feq_dir(kk, rho1[t], ux, uy, uz, eq_kind), ref1);
         });
     }
 }
 
 template <typename S>
-__global__ void set_pops_kernel(S *dst, const uint32_t *links, const double *f, int nx, int ny, int nz,
-                                int64_t plane, double ref0, double ref1) {
+__global__ void set_pops_kernel(S *dst, const uint32_t *links, const int32_t *idx, const double *f, int nx, int ny,
+                                int nz, int64_t plane, double ref0, double ref1) {
     const int64_t N = (int64_t)nx * ny * nz;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t L = links[s];
         if (L & 1u) continue;
+        const int64_t k = idx[s];
         int x, y, z;
         site_coords(s, nx, ny, x, y, z);
         sfor<19>([&](auto I) {
             constexpr int j = I;
             const bool wall = j != 0 && ((L >> opp_of(j)) & 1u);
             const int64_t t = wall ? s : site_shift(x, y, z, cx_of(j), cy_of(j), cz_of(j), nx, ny, nz);
-            const int k = wall ? opp_of(j) : j;
+            const int kk = wall ? opp_of(j) : j;
 #pragma unroll
             for (int d = 0; d < 2; ++d)
-                store_pop<S>(dst, plane, d, j, s, f[(int64_t)(d * 19 + k) * N + t], d == 0 ? ref0 : ref1);
+                store_pop<S>(dst, plane, d, j, k, f[(int64_t)(d * 19 + kk) * N + t], d == 0 ? ref0 : ref1);
         });
     }
 }
 
 template <typename S>
-__global__ void get_pops_kernel(const S *src, const uint32_t *links, double *f, int nx, int ny, int nz,
-                                int64_t plane, double ref0, double ref1) {
+__global__ void get_pops_kernel(const S *src, const uint32_t *links, const int32_t *idx, double *f, int nx, int ny,
+                                int nz, int64_t plane, double ref0, double ref1) {
     const int64_t N = (int64_t)nx * ny * nz;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t L = links[s];
+        if (L & 1u) {
+#pragma unroll
+            for (int q = 0; q < 38; ++q) f[(int64_t)q * N + s] = 0.0;
+            continue;
+        }
         int x, y, z;
         site_coords(s, nx, ny, x, y, z);
         sfor<19>([&](auto I) {
@@ -777,11 +783,10 @@ __global__ void get_pops_kernel(const S *src, const uint32_t *links, double *f, 
             // f_i(x) = f*_i(x - c_i) if x - c_i is fluid, else f*_opp(i)(x).
             const bool wall = i != 0 && ((L >> i) & 1u);
             const int64_t t = wall ? s : site_shift(x, y, z, -cx_of(i), -cy_of(i), -cz_of(i), nx, ny, nz);
-            const int k = wall ? opp_of(i) : i;
+            const int kk = wall ? opp_of(i) : i;
+            const int64_t k = idx[t];   // t is fluid here
 #pragma unroll
-            for (int d = 0; d < 2; ++d)
-                f[(int64_t)(d * 19 + i) * N + s] =
-                    (L & 1u) ? 0.0 : load_pop<S>(src, plane, d, k, t, d == 0 ? ref0 : ref1);
+            for (int d = 0; d < 2; ++d) f[(int64_t)(d * 19 + i) * N + s] = load_pop<S>(src, plane, d, kk, k, d == 0 ? ref0 : ref1);
         });
     }
 }
@@ -797,7 +802,7 @@ KArgs<S> make_kargs(const StepLaunch &L) {
     KArgs<S> a;
     a.src = static_cast<const S *>(L.src);
     a.dst = static_cast<S *>(L.dst);
-    a.links = L.links;
+    a.idx = L.idx;
     a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
     a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk;
     a.plane_bytes = (uint32_t)(L.plane * (int64_t)sizeof(S));
@@ -925,31 +930,31 @@ hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, i
     default: return hipErrorInvalidValue;                       \
     }
 
-hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const double *rho0, const double *rho1,
-                              const double *u, int nx, int ny, int nz, int64_t plane, int eq_kind, const double ref[2],
-                              hipStream_t s) {
+hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
+                              const double *rho1, const double *u, int nx, int ny, int nz, int64_t plane, int eq_kind,
+                              const double ref[2], hipStream_t s) {
     const int g = site_grid((int64_t)nx * ny * nz);
     LBM_DISPATCH_PREC(prec, S,
                       hipLaunchKernelGGL(init_fields_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<S *>(dst), links,
-                                         rho0, rho1, u, nx, ny, nz, plane, eq_kind, ref[0], ref[1]));
+                                         idx, rho0, rho1, u, nx, ny, nz, plane, eq_kind, ref[0], ref[1]));
     return hipGetLastError();
 }
 
-hipError_t launch_set_pops(int prec, void *dst, const uint32_t *links, const double *f, int nx, int ny, int nz,
-                           int64_t plane, const double ref[2], hipStream_t s) {
+hipError_t launch_set_pops(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *f, int nx,
+                           int ny, int nz, int64_t plane, const double ref[2], hipStream_t s) {
     const int g = site_grid((int64_t)nx * ny * nz);
     LBM_DISPATCH_PREC(prec, S,
-                      hipLaunchKernelGGL(set_pops_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<S *>(dst), links, f,
-                                         nx, ny, nz, plane, ref[0], ref[1]));
+                      hipLaunchKernelGGL(set_pops_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<S *>(dst), links,
+                                         idx, f, nx, ny, nz, plane, ref[0], ref[1]));
     return hipGetLastError();
 }
 
-hipError_t launch_get_pops(int prec, const void *src, const uint32_t *links, double *f, int nx, int ny, int nz,
-                           int64_t plane, const double ref[2], hipStream_t s) {
+hipError_t launch_get_pops(int prec, const void *src, const uint32_t *links, const int32_t *idx, double *f, int nx,
+                           int ny, int nz, int64_t plane, const double ref[2], hipStream_t s) {
     const int g = site_grid((int64_t)nx * ny * nz);
     LBM_DISPATCH_PREC(prec, S,
                       hipLaunchKernelGGL(get_pops_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<const S *>(src),
-                                         links, f, nx, ny, nz, plane, ref[0], ref[1]));
+                                         links, idx, f, nx, ny, nz, plane, ref[0], ref[1]));
     return hipGetLastError();
 }
 
