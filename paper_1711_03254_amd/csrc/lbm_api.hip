@@ -359,9 +359,9 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
     // Each plane starts 256-byte aligned; the odd padding keeps the 38 planes
     // of a buffer from starting at the same offsets modulo large powers of two.
     c->plane = (nfl + 127) / 128 * 128 + 128 * 13;
-    // The step addresses a component's 19 planes with 32-bit byte offsets.
-    if (19 * (uint64_t)c->plane * esz >= (1ull << 32))
-        return bail(fail(c, LBM_EINVAL, "lattice too large: the 19 planes of one component must stay below 4 GiB"));
+    // The step addresses 11 planes of component pairs with 32-bit byte offsets.
+    if (11 * 2 * (uint64_t)c->plane * esz >= (1ull << 32))
+        return bail(fail(c, LBM_EINVAL, "lattice too large: 11 population planes must stay below 4 GiB"));
 
     const size_t fbytes = (size_t)2 * 19 * c->plane * esz;
     for (int k = 0; k < 2; ++k) {

@@ -30,7 +30,8 @@ struct StepLaunch {
     void *dst;
     const int32_t *idx;     // compact population index of each lattice site, -1 where solid
     int nx, ny, nz;
-    int64_t plane;          // elements per (component, direction) plane (fluid sites plus padding)
+    int64_t plane;          // sites per direction plane (fluid sites plus padding); a plane holds
+                            // the pairs (component 1, component 2) of those sites
     int tile_x, tile_y, zchunk;
     int ntx, nty, nzc;      // tiles in x, y and chunks in z
     double tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;

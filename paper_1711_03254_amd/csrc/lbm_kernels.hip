@@ -3,8 +3,9 @@
 //
 // Storage: populations exist for fluid sites only.  Each fluid site has a
 // compact index k (the host numbers them tile column by tile column, z
-// plane by plane, so that a block's sites are contiguous); per
-// (component, direction) plane the populations are an array over k.  The
+// plane by plane, so that a block's sites are contiguous); the plane of
+// direction i holds, for every k, the pair (f^1_i, f^2_i) of the two
+// components, which a pull reads from the same source site.  The
 // buffer a step reads holds the post-collision populations f*(x, t-1) of
 // the previous step; the step pulls f_i(x, t) = f*_i(x - c_i) (or, when
 // x - c_i is solid, the reversed population f*_opp(i)(x): halfway
@@ -96,7 +97,7 @@ struct KArgs {
     S *dst;
     const int32_t *idx;     // compact index of each lattice site, -1 where solid
     int nx, ny, nz, ntx, nty, zchunk;
-    uint32_t plane_bytes;   // bytes of one (component, direction) plane
+    uint32_t plane_bytes;   // bytes of one direction's plane of component pairs
     C tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
     int eq_kind, force_kind;
     double *partials;
@@ -109,44 +110,62 @@ __device__ __forceinline__ int wrap(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-// Raw buffer access.  One buffer resource spans the 19 planes of one
-// component; the scalar offset selects a plane and the 32-bit lane offset a
-// site in it.  Every access issued is in bounds (lanes without work are
-// masked off), so the resource's range check never applies.
+// Raw buffer access.  A population plane holds, per compact site index k,
+// the pair (f^1_i, f^2_i) of the two components, so one access moves both.
+// Two buffer resources cover a buffer: planes 0-10 and planes 11-18 (each
+// opposite pair within one); the scalar offset selects the plane and the
+// 32-bit lane offset the site.  Every access issued is in bounds (lanes
+// without work are masked off), so the range check never applies.
 constexpr int kRsrcWord3 = 0x00020000;   // gfx9 raw (unswizzled) buffer
 constexpr int kNonTemporal = 2;          // cache policy of the population stores
+constexpr int kSplit = 11;               // first plane of the second resource
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t component_rsrc(const void *base, int d, uint32_t pb) {
-    char *p = const_cast<char *>(static_cast<const char *>(base)) + (size_t)d * 19 * pb;
-    return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)(19u * pb), kRsrcWord3);
-}
-
-template <typename S> __device__ __forceinline__ S buf_load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s);
-template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
-}
-template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
-}
-template <> __device__ __forceinline__ __half buf_load<__half>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
-}
-template <>
-__device__ __forceinline__ __hip_bfloat16 buf_load<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(__hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t half_rsrc(const void *base, int h, uint32_t pb) {
+    char *p = const_cast<char *>(static_cast<const char *>(base)) + (h ? (size_t)kSplit * pb : 0);
+    return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)((h ? 19 - kSplit : kSplit) * pb), kRsrcWord3);
 }
 
-// Write-once streaming store of a post-collision population (read again
-// only in the next step, so it should not displace reused lines).
-template <typename S> __device__ __forceinline__ void buf_store(S x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+// Loads the pair of plane-relative byte offset v + s.  The loaded vector is
+// reinterpreted as a whole (an integer or a struct) before it is split:
+// extracting its elements one by one lets the compiler narrow the load to
+// its first element.
+struct U64Pair {
+    uint64_t a, b;
+};
+template <typename S>
+__device__ __forceinline__ void pair_load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, S &a, S &b) {
     if constexpr (std::is_same_v<S, float>) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, v, s, kNonTemporal);
+        const uint64_t x = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+        a = __builtin_bit_cast(float, (uint32_t)(x & 0xffffffffu));
+        b = __builtin_bit_cast(float, (uint32_t)(x >> 32));
     } else if constexpr (std::is_same_v<S, double>) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v, s, kNonTemporal);
+        const U64Pair x = __builtin_bit_cast(U64Pair, __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0));
+        a = __builtin_bit_cast(double, x.a);
+        b = __builtin_bit_cast(double, x.b);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, kNonTemporal);
+        const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0);
+        a = __builtin_bit_cast(S, (unsigned short)(x & 0xffffu));
+        b = __builtin_bit_cast(S, (unsigned short)(x >> 16));
+    }
+}
+
+// Write-once streaming store of a post-collision pair (read again only in
+// the next step, so it should not displace reused lines).
+template <typename S>
+__device__ __forceinline__ void pair_store(S a, S b, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    if constexpr (std::is_same_v<S, float>) {
+        const uint64_t x = (uint64_t)__builtin_bit_cast(uint32_t, a) | ((uint64_t)__builtin_bit_cast(uint32_t, b) << 32);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v, s, kNonTemporal);
+    } else if constexpr (std::is_same_v<S, double>) {
+        const U64Pair x{__builtin_bit_cast(uint64_t, a), __builtin_bit_cast(uint64_t, b)};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), r, v, s, kNonTemporal);
+    } else {
+        const uint32_t x = (uint32_t)__builtin_bit_cast(unsigned short, a) |
+                           ((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
+        __builtin_amdgcn_raw_buffer_store_b32(x, r, v, s, kNonTemporal);
     }
 }
 
@@ -247,11 +266,20 @@ struct CompState {
 // the part E even under c -> -c and the odd part O:
 // f*_i = w (E + O), f*_opp(i) = w (E - O), with P_i split the same way
 // (peven, podd per pair).  The terms are scaled by the weights up front and
-// only the non-zero components of c_i enter.  `put(i, value)` stores one
-// population; 16-bit storage subtracts w_i ref here.
-template <typename C, typename Put>
-__device__ __forceinline__ void collide_component(const CompState<C> &st, C ux, C uy, C uz, C r2, C keep, C guo,
-                                                  C pe0, const C (&podd)[9], const C (&peven)[9], Put &&put) {
+// only the non-zero components of c_i enter; 16-bit storage subtracts
+// w_i ref here.
+template <typename C>
+struct Collide {
+    C f0;                                    // the rest population
+    C Ax, Ay, Az;                            // axis pairs: 4.5 w (X_aa - t) - w ref
+    C Dxy, Dxz, Dyz, Qxy, Qxz, Qyz;          // diagonal pairs: 4.5 w (X_aa + X_bb - t) - w ref, 4.5 w X_ab
+    C F18x, F18y, F18z, F36x, F36y, F36z;    // 1.5 w F
+    C r18, r36;                              // w rho
+};
+
+template <typename C>
+__device__ __forceinline__ Collide<C> collide_prep(const CompState<C> &st, C ux, C uy, C uz, C r2, C keep, C guo,
+                                                   C pe0) {
     constexpr C T0 = C(1.0 / 3.0);
     const Moments<C> &m = *st.m;
     const C rho = st.rho, Fx = st.Fx, Fy = st.Fy, Fz = st.Fz;
@@ -268,41 +296,45 @@ __device__ __forceinline__ void collide_component(const CompState<C> &st, C ux, 
     const C tr = Xxx + Xyy + Xzz;
     const C t = T0 * tr;
     const C ref = st.ref;
-
-    // rest population: w_0 = 1/3, c = 0
-    put(0, C(1.0 / 3.0) * (rho * pe0 - ref) - C(0.5) * tr);
-
-    // axis pairs (w = 1/18): 4.5 w (X_aa - t) - w ref and 1.5 w F_a
     const C ref18 = ref * C(1.0 / 18.0), ref36 = ref * C(1.0 / 36.0);
-    const C Ax = C(0.25) * (Xxx - t) - ref18, Ay = C(0.25) * (Xyy - t) - ref18, Az = C(0.25) * (Xzz - t) - ref18;
-    // diagonal pairs (w = 1/36): 4.5 w (X_aa + X_bb - t) - w ref and 4.5 w 2 X_ab
-    const C Dxy = C(0.125) * (Xxx + Xyy - t) - ref36, Dxz = C(0.125) * (Xxx + Xzz - t) - ref36,
-            Dyz = C(0.125) * (Xyy + Xzz - t) - ref36;
-    const C Qxy = C(0.25) * Xxy, Qxz = C(0.25) * Xxz, Qyz = C(0.25) * Xyz;
-    const C F18x = Fx * C(1.0 / 12.0), F18y = Fy * C(1.0 / 12.0), F18z = Fz * C(1.0 / 12.0);
-    const C F36x = Fx * C(1.0 / 24.0), F36y = Fy * C(1.0 / 24.0), F36z = Fz * C(1.0 / 24.0);
-    const C r18 = rho * C(1.0 / 18.0), r36 = rho * C(1.0 / 36.0);
+    Collide<C> c;
+    c.f0 = C(1.0 / 3.0) * (rho * pe0 - ref) - C(0.5) * tr;   // w_0 = 1/3, c = 0
+    c.Ax = C(0.25) * (Xxx - t) - ref18;
+    c.Ay = C(0.25) * (Xyy - t) - ref18;
+    c.Az = C(0.25) * (Xzz - t) - ref18;
+    c.Dxy = C(0.125) * (Xxx + Xyy - t) - ref36;
+    c.Dxz = C(0.125) * (Xxx + Xzz - t) - ref36;
+    c.Dyz = C(0.125) * (Xyy + Xzz - t) - ref36;
+    c.Qxy = C(0.25) * Xxy;
+    c.Qxz = C(0.25) * Xxz;
+    c.Qyz = C(0.25) * Xyz;
+    c.F18x = Fx * C(1.0 / 12.0); c.F18y = Fy * C(1.0 / 12.0); c.F18z = Fz * C(1.0 / 12.0);
+    c.F36x = Fx * C(1.0 / 24.0); c.F36y = Fy * C(1.0 / 24.0); c.F36z = Fz * C(1.0 / 24.0);
+    c.r18 = rho * C(1.0 / 18.0);
+    c.r36 = rho * C(1.0 / 36.0);
+    return c;
+}
 
-    sfor<9>([&](auto K) {
-        constexpr int k = K;
-        constexpr int i = 2 * k + 1;
-        constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
-        C ew, ow;   // w E and w O
-        if constexpr (i <= 6) {
-            const C A = X != 0 ? Ax : (Y != 0 ? Ay : Az);
-            const C Fa = X != 0 ? F18x : (Y != 0 ? F18y : F18z);
-            ew = r18 * peven[k] + A;
-            ow = r18 * podd[k] + Fa;   // c_a = +1 for the odd member
-        } else {
-            const C D = (X != 0 && Y != 0) ? Dxy : (X != 0 ? Dxz : Dyz);
-            const C Q = (X != 0 && Y != 0) ? Qxy : (X != 0 ? Qxz : Qyz);
-            constexpr int sg = X * Y + X * Z + Y * Z;   // product of the two non-zero components
-            ew = r36 * peven[k] + (sg > 0 ? D + Q : D - Q);
-            ow = r36 * podd[k] + dot_signed<X, Y, Z>(F36x, F36y, F36z);
-        }
-        put(i, ew + ow);
-        put(i + 1, ew - ow);
-    });
+// f*_i and f*_opp(i) of the opposite pair k (odd member i = 2k + 1).
+template <int k, typename C>
+__device__ __forceinline__ void collide_pair(const Collide<C> &c, C podd, C peven, C &plus, C &minus) {
+    constexpr int i = 2 * k + 1;
+    constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+    C ew, ow;   // w E and w O
+    if constexpr (i <= 6) {
+        const C A = X != 0 ? c.Ax : (Y != 0 ? c.Ay : c.Az);
+        const C Fa = X != 0 ? c.F18x : (Y != 0 ? c.F18y : c.F18z);
+        ew = c.r18 * peven + A;
+        ow = c.r18 * podd + Fa;   // c_a = +1 for the odd member
+    } else {
+        const C D = (X != 0 && Y != 0) ? c.Dxy : (X != 0 ? c.Dxz : c.Dyz);
+        const C Q = (X != 0 && Y != 0) ? c.Qxy : (X != 0 ? c.Qxz : c.Qyz);
+        constexpr int sg = X * Y + X * Z + Y * Z;   // product of the two non-zero components
+        ew = c.r36 * peven + (sg > 0 ? D + Q : D - Q);
+        ow = c.r36 * podd + dot_signed<X, Y, Z>(c.F36x, c.F36y, c.F36z);
+    }
+    plus = ew + ow;
+    minus = ew - ow;
 }
 
 // ---------------------------------------------------------------------------
@@ -338,7 +370,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
 
     __shared__ C psi0[4][RH][RW];
     __shared__ C psi1[4][RH][RW];
-    // byte offset k * ESZ of each site's populations within a plane, -1 where solid
+    // byte offset of each site's population pair within a plane, -1 where solid
     __shared__ int kid[5][HH][HW];
     __shared__ double red[NT / 64][6];
 
@@ -390,10 +422,10 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     auto store_idx = [&](int q, const int (&v)[NE]) {
 #pragma unroll
         for (int j = 0; j < NE; ++j)
-            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? v[j] * (int)ESZ : -1;
+            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? v[j] * (int)(2 * ESZ) : -1;
     };
 
-    const __amdgpu_buffer_rsrc_t src0 = component_rsrc(a.src, 0, pb), src1 = component_rsrc(a.src, 1, pb);
+    const __amdgpu_buffer_rsrc_t srcA = half_rsrc(a.src, 0, pb), srcB = half_rsrc(a.src, 1, pb);
 
     // Pull of the site at index-tile position (hr, hc) whose populations sit
     // at byte offset self, planes zw - 1, zw, zw + 1 in index slots qm, q0,
@@ -405,7 +437,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
         sfor<19>([&](auto I) {
             constexpr int i = I;
             constexpr int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-            const uint32_t soff = (uint32_t)lo * pb;
+            const uint32_t soff = (uint32_t)(lo < kSplit ? lo : lo - kSplit) * pb;
             uint32_t off;
             if constexpr (i == 0) {
                 off = self;
@@ -416,8 +448,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                 if constexpr (i == lo) off = nb >= 0 ? (uint32_t)nb : self_p;
                 else off = nb >= 0 ? (uint32_t)nb + pb : self;
             }
-            raw[0][i] = buf_load<S>(src0, off, soff);
-            raw[1][i] = buf_load<S>(src1, off, soff);
+            pair_load<S>(lo < kSplit ? srcA : srcB, off, soff, raw[0][i], raw[1][i]);
         });
     };
 
@@ -496,7 +527,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     kc = kn;
     __syncthreads();
 
-    const __amdgpu_buffer_rsrc_t dst0 = component_rsrc(a.dst, 0, pb), dst1 = component_rsrc(a.dst, 1, pb);
+    const __amdgpu_buffer_rsrc_t dstA = half_rsrc(a.dst, 0, pb), dstB = half_rsrc(a.dst, 1, pb);
 
     for (int z = z0; z < z1; ++z) {
         const int sm = (z - z0) & 3, s0 = (z - z0 + 1) & 3, sp = (z - z0 + 2) & 3;
@@ -579,13 +610,25 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                 });
 
                 const uint32_t vo = (uint32_t)kc;
-                auto put0 = [&](int i, C v) { buf_store<S>(Codec<S>::st(v), dst0, vo, (uint32_t)i * pb); };
-                auto put1 = [&](int i, C v) { buf_store<S>(Codec<S>::st(v), dst1, vo, (uint32_t)i * pb); };
+                auto put = [&](auto I, C v0, C v1) {
+                    constexpr int i = I;
+                    pair_store<S>(Codec<S>::st(v0), Codec<S>::st(v1), i < kSplit ? dstA : dstB, vo,
+                                  (uint32_t)(i < kSplit ? i : i - kSplit) * pb);
+                };
                 const C sref0 = Codec<S>::shifted ? ref0 : C(0), sref1 = Codec<S>::shifted ? ref1 : C(0);
                 const CompState<C> st0{rho[0], Fx[0], Fy[0], Fz[0], &mc[0], sref0};
                 const CompState<C> st1{rho[1], Fx[1], Fy[1], Fz[1], &mc[1], sref1};
-                collide_component(st0, ux, uy, uz, r2, keep, guo, pe0, podd, peven, put0);
-                collide_component(st1, ux, uy, uz, r2, keep, guo, pe0, podd, peven, put1);
+                const Collide<C> c0 = collide_prep(st0, ux, uy, uz, r2, keep, guo, pe0);
+                const Collide<C> c1 = collide_prep(st1, ux, uy, uz, r2, keep, guo, pe0);
+                put(std::integral_constant<int, 0>{}, c0.f0, c1.f0);
+                sfor<9>([&](auto K) {
+                    constexpr int k = K;
+                    C p0, m0, p1, m1;
+                    collide_pair<k>(c0, podd[k], peven[k], p0, m0);
+                    collide_pair<k>(c1, podd[k], peven[k], p1, m1);
+                    put(std::integral_constant<int, 2 * k + 1>{}, p0, p1);
+                    put(std::integral_constant<int, 2 * k + 2>{}, m0, m1);
+                });
             }
         }
 
@@ -707,12 +750,12 @@ __device__ __forceinline__ double feq_dir(int i, double rho, double ux, double u
 template <typename S>
 __device__ __forceinline__ void store_pop(S *dst, int64_t plane, int d, int i, int64_t k, double v, double ref) {
     if constexpr (Codec<S>::shifted) v -= w_of(i) * ref;
-    dst[(int64_t)(d * 19 + i) * plane + k] = Codec<S>::st((typename Codec<S>::C)v);
+    dst[((int64_t)i * plane + k) * 2 + d] = Codec<S>::st((typename Codec<S>::C)v);
 }
 
 template <typename S>
 __device__ __forceinline__ double load_pop(const S *src, int64_t plane, int d, int i, int64_t k, double ref) {
-    double v = (double)Codec<S>::ld(src[(int64_t)(d * 19 + i) * plane + k]);
+    double v = (double)Codec<S>::ld(src[((int64_t)i * plane + k) * 2 + d]);
     if constexpr (Codec<S>::shifted) v += w_of(i) * ref;
     return v;
 }
@@ -805,7 +848,7 @@ KArgs<S> make_kargs(const StepLaunch &L) {
     a.idx = L.idx;
     a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
     a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk;
-    a.plane_bytes = (uint32_t)(L.plane * (int64_t)sizeof(S));
+    a.plane_bytes = (uint32_t)(L.plane * 2 * (int64_t)sizeof(S));   // a plane of component pairs
     a.tau0 = (C)L.tau0; a.tau1 = (C)L.tau1; a.G = (C)L.G;
     a.gx = (C)L.gx; a.gy = (C)L.gy; a.gz = (C)L.gz;
     a.wall0 = (C)L.wall0; a.wall1 = (C)L.wall1; a.ref0 = (C)L.ref0; a.ref1 = (C)L.ref1;
