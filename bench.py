@@ -116,6 +116,30 @@ def cpu_baseline(solid, rA, rB, phys, steps=3):
             "sample": f"the full {n}^3 workload, {steps} steps of the FP64 oracle ({dt:.1f} s)"}
 
 
+WEIGHTS = os.path.join(ROOT, "paper_1711_03254_amd", "weights", "surrogate_mixture_b32.npz")
+
+
+def warm_start(lbm):
+    """Time to steady state, cold and with the learned warm start, on one
+    held-out 128^3 mixture subvolume (the surrogate's workload), FP32 to a
+    residual of 1e-5 and FP64 to 1e-6."""
+    from paper_1711_03254_amd import inputs, surrogate, warmstart as ws
+    if not os.path.exists(WEIGHTS):
+        return None
+    net = surrogate.Surrogate.load(WEIGHTS)
+    phys = ws.physics()
+    solid, ra0, rb0, info = inputs.mixture_case(128, 10100)
+    out = {"workload": f"mixture subvolume 128^3, seed 10100, {json.dumps(info)}, G=0, g=1e-4 z",
+           "network": {"params": net.n_params, "weights": os.path.relpath(WEIGHTS, ROOT)}}
+    for prec, tol in (("fp32", 1e-5), ("fp64", 1e-6)):
+        r = ws.compare(net, dict(solid=solid, ra0=ra0, rb0=rb0), phys, tol, prec=prec)
+        r["tolerance"] = tol
+        r["steps_factor"] = r["cold_steps"] / r["warm_steps"]
+        r["time_factor"] = r["cold_seconds"] / (r["warm_seconds"] + r["predict_seconds"])
+        out[prec] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+    return out
+
+
 def traffic_for(kern_ms_unused, n_fluid):
     """HBM bytes per step launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
@@ -138,6 +162,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--G", type=float, default=-4.2)
     ap.add_argument("--interface-width", type=float, default=1.5)
+    ap.add_argument("--no-warm-start", dest="warm_start", action="store_false",
+                    help="skip the cold / warm time-to-steady-state comparison")
     ap.add_argument("--no-all-fluid", dest="all_fluid", action="store_false",
                     help="skip the all-fluid lattice of the same size")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -185,6 +211,10 @@ def main():
             r = time_precision(lbm, torch, prec, zero, dA, dB, phys_af, max(50, args.steps // 2), args.warmup, 0)
             allf[prec] = {k: r[k] for k in ("kernel_ms", "kernel_mlups", "algorithmic_GBs", "hbm_frac")}
             print(f"# all-fluid {prec}: {json.dumps(allf[prec])}", file=sys.stderr, flush=True)
+    ws_res = None
+    if args.warm_start:
+        ws_res = warm_start(lbm)
+        print(f"# warm start: {json.dumps(ws_res)}", file=sys.stderr, flush=True)
     main_r = res["fp32"]
     n_fluid = main_r["n_fluid"]
     roof = {
@@ -227,6 +257,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "all_fluid": {k: {kk: round(v, 4) for kk, v in r.items()} for k, r in allf.items()},
+        "warm_start": ws_res,
         "precisions": {k: {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()}
                        for k, r in res.items()},
     }

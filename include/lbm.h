@@ -89,14 +89,19 @@ typedef struct {
     const double *u_init;        /* 3N (component-major) initial velocity, or NULL for rest */
     void *stream;                /* hipStream_t to run on; NULL = a stream the library creates */
     int32_t tile_x, tile_y;      /* x-y tile of the step kernel (0 = library default; 64x4, 32x8,
-                                    16x16 or 8x32) */
+                                    16x16, 8x32, 64x8 or 32x16) */
     int32_t zchunk;              /* z planes per block (0 = library default) */
 } lbm_params;
 
 /* Creates a context: validates p, allocates the device state and sets the
  * populations to the equilibrium f = f_eq(rho_init, u_init) (Eq. 3; the
  * paper does not state the initial populations).  Records the initial
- * component masses for the periodic check.  On failure *out is NULL. */
+ * component masses for the periodic check.  On failure *out is NULL.
+ * Size limits (LBM_EINVAL): fewer than 2^30 sites, and 11 direction planes
+ * of the fluid sites' populations below 4 GiB (about 24 M fluid sites at
+ * FP64, 48 M at FP32, 97 M with 16-bit storage).  Device memory: two
+ * population buffers of 2 x 19 x n_fluid x storage bytes, plus 8 bytes
+ * per site for the link mask and the site index. */
 int lbm_init(const lbm_params *p, lbm_ctx **out);
 
 /* Advances n >= 0 time steps (Eqs. 1-11).  Every check_every steps the step

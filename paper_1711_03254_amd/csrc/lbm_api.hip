@@ -311,7 +311,7 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         return fail(nullptr, LBM_EINVAL, "mass_tol must be >= 0 and rho_ref finite");
     if (!p.rho_init[0] || !p.rho_init[1]) return fail(nullptr, LBM_EINVAL, "rho_init pointers are NULL");
     if ((p.tile_x || p.tile_y) && !lbm::tile_supported(p.tile_x, p.tile_y))
-        return fail(nullptr, LBM_EINVAL, "unsupported tile (64x4, 32x8, 16x16 or 8x32)");
+        return fail(nullptr, LBM_EINVAL, "unsupported tile (64x4, 32x8, 16x16, 8x32, 64x8 or 32x16)");
     if (p.zchunk < 0) return fail(nullptr, LBM_EINVAL, "zchunk must be >= 0");
 
     lbm_ctx *c = new (std::nothrow) lbm_ctx();

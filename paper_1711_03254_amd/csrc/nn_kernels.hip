@@ -1,0 +1,451 @@
+// nn_kernels.hip -- gfx950 kernels of the warm-start surrogate (include/lbm_nn.h):
+// a 3 x 3 x 3 periodic convolution as an implicit GEMM on the matrix cores
+// (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32 accumulation), its weight
+// gradient, and the element-wise pieces of training (ReLU mask, pooling,
+// upsampling, loss, Adam).
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "../../include/lbm.h"
+#include "../../include/lbm_nn.h"
+
+namespace {
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    return __builtin_bit_cast(uint16_t, __float2bfloat16(f));   // round to nearest even
+}
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Four consecutive bf16 values (8 bytes, 8-byte aligned) as an MFMA operand.
+__device__ __forceinline__ s16x4 load4(const uint16_t *p) {
+    return __builtin_bit_cast(s16x4, *reinterpret_cast<const uint2 *>(p));
+}
+
+// ---------------------------------------------------------------------------
+// Forward convolution.  GEMM view: out[co][p] = sum_k A[co][k] B[k][p] with
+// k = (t, ci).  A wave computes 16 output channels x 64 positions as four
+// 16 x 16 tiles that share the A operand (the weights of one tap and 16 input
+// channels); a block is four waves along positions.  Operand layout of the
+// 16x16x16 instruction: lane l supplies A[l % 16][4 (l / 16) + j] and
+// B[4 (l / 16) + j][l % 16] (j = 0..3) and receives D[4 (l / 16) + j][l % 16].
+// ---------------------------------------------------------------------------
+template <bool OUT_F32>
+__global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict__ x, int ldx,
+                                                     const uint16_t *__restrict__ w, const float *__restrict__ bias,
+                                                     void *__restrict__ y, int ldy, int relu, int nb, int D, int H,
+                                                     int W, int ci, int co) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int co0 = blockIdx.y * 16;
+    const int64_t P = (int64_t)nb * D * H * W;
+    const int64_t pbase = (int64_t)blockIdx.x * 256 + wv * 64;
+    const int col = lane & 15, kq = 4 * (lane >> 4);
+
+    int pb[4], pz[4], py[4], px[4];
+    bool valid[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const int64_t p = pbase + 16 * f + col;
+        valid[f] = p < P;
+        int64_t q = valid[f] ? p : 0;
+        px[f] = (int)(q % W); q /= W;
+        py[f] = (int)(q % H); q /= H;
+        pz[f] = (int)(q % D);
+        pb[f] = (int)(q / D);
+    }
+    f32x4 acc[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) acc[f] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const s16x4 zero4 = {0, 0, 0, 0};
+    for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const uint16_t *src[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int64_t s = (((int64_t)pb[f] * D + wrapi(pz[f] + dz, D)) * H + wrapi(py[f] + dy, H)) * W +
+                              wrapi(px[f] + dx, W);
+            src[f] = x + s * ldx + kq;
+        }
+        const uint16_t *wa = w + ((int64_t)t * co + co0 + col) * ci + kq;
+        for (int c0 = 0; c0 < ci; c0 += 16) {
+            const s16x4 a = load4(wa + c0);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const s16x4 b = valid[f] ? load4(src[f] + c0) : zero4;
+                acc[f] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[f], 0, 0, 0);
+            }
+        }
+    }
+    // lane holds channels co0 + kq + j of position pbase + 16 f + col
+    float bj[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bj[j] = bias ? bias[co0 + kq + j] : 0.f;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (!valid[f]) continue;
+        const int64_t p = pbase + 16 * f + col;
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = acc[f][j] + bj[j];
+            if (relu) v[j] = v[j] > 0.f ? v[j] : 0.f;
+        }
+        if constexpr (OUT_F32) {
+            *reinterpret_cast<float4 *>(static_cast<float *>(y) + p * ldy + co0 + kq) = float4{v[0], v[1], v[2], v[3]};
+        } else {
+            const uint32_t lo = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+            const uint32_t hi = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+            *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(y) + p * ldy + co0 + kq) = uint2{lo, hi};
+        }
+    }
+}
+
+__global__ void flip_kernel(const uint16_t *w, uint16_t *wt, int ci, int co) {
+    const int64_t n = 27LL * ci * co;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e % ci);
+        const int o = (int)((e / ci) % co);
+        const int t = (int)(e / ((int64_t)ci * co));
+        wt[((int64_t)(26 - t) * ci + c) * co + o] = w[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient.  GEMM view per tap: dW[co][ci] = sum_p A[co][p] B[p][ci]
+// with A = dy^T and B = x shifted by the tap.  A wave owns one (tap, 16 co,
+// 16 ci) tile and one chunk of positions and writes its partial tile to
+// work[chunk]; a second kernel sums the chunks in order.
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 4096;   // positions per partial sum
+
+__global__ void __launch_bounds__(256) bwd_weight_kernel(const uint16_t *__restrict__ x, int ldx,
+                                                         const uint16_t *__restrict__ dyv, int lddy,
+                                                         float *__restrict__ work, int nb, int D, int H, int W,
+                                                         int ci, int co, int ntiles) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tile = blockIdx.y * 4 + wv;   // (t, co tile, ci tile)
+    if (tile >= ntiles) return;
+    const int nci = ci / 16, nco = co / 16;
+    const int cit = tile % nci, cot = (tile / nci) % nco, t = tile / (nci * nco);
+    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const int64_t P = (int64_t)nb * D * H * W;
+    const int64_t p0 = (int64_t)blockIdx.x * kChunk;
+    const int64_t p1 = p0 + kChunk < P ? p0 + kChunk : P;
+    const int col = lane & 15, kq = 4 * (lane >> 4);
+    const int cA = cot * 16 + col, cB = cit * 16 + col;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t pk = p0; pk < p1; pk += 16) {
+        short av[4], bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t p = pk + kq + j;
+            if (p < p1) {
+                int64_t q = p;
+                const int xx = (int)(q % W); q /= W;
+                const int yy = (int)(q % H); q /= H;
+                const int zz = (int)(q % D);
+                const int bb = (int)(q / D);
+                const int64_t s = (((int64_t)bb * D + wrapi(zz + dz, D)) * H + wrapi(yy + dy, H)) * W + wrapi(xx + dx, W);
+                av[j] = (short)dyv[p * lddy + cA];
+                bv[j] = (short)x[s * ldx + cB];
+            } else {
+                av[j] = 0;
+                bv[j] = 0;
+            }
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(s16x4{av[0], av[1], av[2], av[3]},
+                                                        s16x4{bv[0], bv[1], bv[2], bv[3]}, acc, 0, 0, 0);
+    }
+    // lane holds dW[co = cot 16 + kq + j][ci = cit 16 + col]
+    float *out = work + (int64_t)blockIdx.x * 27 * co * ci;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[((int64_t)t * co + cot * 16 + kq + j) * ci + cB] = acc[j];
+}
+
+// db partials: one per chunk and channel.
+__global__ void bwd_bias_kernel(const uint16_t *dyv, int lddy, float *work, int64_t P, int co) {
+    const int c = threadIdx.x;   // blockDim.x = co (<= 1024)
+    const int64_t p0 = (int64_t)blockIdx.x * kChunk;
+    const int64_t p1 = p0 + kChunk < P ? p0 + kChunk : P;
+    float s = 0.f;
+    for (int64_t p = p0; p < p1; ++p) s += bf16_to_f32(dyv[p * lddy + c]);
+    work[(int64_t)blockIdx.x * co + c] = s;
+}
+
+// out[e] = sum over chunks of part[chunk][e], chunks in order.
+__global__ void sum_chunks_kernel(const float *part, int nchunks, int64_t n, float *out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int k = 0; k < nchunks; ++k) s += part[(int64_t)k * n + e];
+        out[e] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Element-wise pieces.
+// ---------------------------------------------------------------------------
+__global__ void relu_bwd_cast_kernel(const float *dy, int lddy, const uint16_t *yv, int ldy, uint16_t *out, int ldo,
+                                     int64_t P, int c, int relu) {
+    const int64_t n = P * c;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / c;
+        const int k = (int)(e % c);
+        float g = dy[p * lddy + k];
+        if (relu && !(bf16_to_f32(yv[p * ldy + k]) > 0.f)) g = 0.f;
+        out[p * ldo + k] = f32_to_bf16(g);
+    }
+}
+
+// Coarse position pc of (b, z, y, x) at half resolution; fine index of child (i, j, k).
+__device__ __forceinline__ int64_t child(int64_t pc, int d2, int h2, int w2, int i, int j, int k) {
+    int64_t q = pc;
+    const int x = (int)(q % w2); q /= w2;
+    const int y = (int)(q % h2); q /= h2;
+    const int z = (int)(q % d2);
+    const int b = (int)(q / d2);
+    return (((int64_t)b * 2 * d2 + 2 * z + i) * 2 * h2 + 2 * y + j) * 2 * w2 + 2 * x + k;
+}
+
+__global__ void pool2_fwd_kernel(const uint16_t *x, int ldx, uint16_t *y, int ldy, int64_t Pc, int d2, int h2, int w2,
+                                 int c) {
+    const int64_t n = Pc * c;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pc = e / c;
+        const int k = (int)(e % c);
+        float s = 0.f;
+        for (int q = 0; q < 8; ++q) s += bf16_to_f32(x[child(pc, d2, h2, w2, q >> 2, (q >> 1) & 1, q & 1) * ldx + k]);
+        y[pc * ldy + k] = f32_to_bf16(0.125f * s);
+    }
+}
+
+__global__ void pool2_bwd_kernel(const float *dy, int lddy, float *dx, int lddx, int accumulate, int64_t Pc, int d2,
+                                 int h2, int w2, int c) {
+    const int64_t n = Pc * c;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pc = e / c;
+        const int k = (int)(e % c);
+        const float g = 0.125f * dy[pc * lddy + k];
+        for (int q = 0; q < 8; ++q) {
+            float *o = dx + child(pc, d2, h2, w2, q >> 2, (q >> 1) & 1, q & 1) * lddx + k;
+            *o = accumulate ? *o + g : g;
+        }
+    }
+}
+
+__global__ void up2_fwd_kernel(const uint16_t *x, int ldx, uint16_t *y, int ldy, int64_t Pc, int d, int h, int w, int c) {
+    const int64_t n = Pc * c;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pc = e / c;
+        const int k = (int)(e % c);
+        const uint16_t v = x[pc * ldx + k];
+        for (int q = 0; q < 8; ++q) y[child(pc, d, h, w, q >> 2, (q >> 1) & 1, q & 1) * ldy + k] = v;
+    }
+}
+
+__global__ void up2_bwd_kernel(const float *dy, int lddy, float *dx, int lddx, int64_t Pc, int d, int h, int w, int c) {
+    const int64_t n = Pc * c;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pc = e / c;
+        const int k = (int)(e % c);
+        float s = 0.f;
+        for (int q = 0; q < 8; ++q) s += dy[child(pc, d, h, w, q >> 2, (q >> 1) & 1, q & 1) * lddy + k];
+        dx[pc * lddx + k] = s;
+    }
+}
+
+// Loss partial sums per block (FP64), then one block sums them in order.
+__global__ void mse_kernel(const float *pred, int ldp, const float *target, int ldt, const float *cw, float *dpred,
+                           int lddp, double *part, int64_t P, int c) {
+    __shared__ double sh[256];
+    const int64_t n = P * c;
+    const float inv = 1.0f / (float)P;
+    double s = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / c;
+        const int k = (int)(e % c);
+        const float r = pred[p * ldp + k] - target[p * ldt + k];
+        dpred[p * lddp + k] = 2.0f * cw[k] * r * inv;
+        s += (double)cw[k] * (double)r * (double)r;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void mse_final_kernel(const double *part, int nparts, int64_t P, double *loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < nparts; ++k) s += part[k];
+        *loss = s / (double)P;
+    }
+}
+
+__global__ void adam_kernel(float *param, const float *grad, float *m, float *v, uint16_t *pb, int64_t n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const float g = grad[e];
+        const float mm = b1 * m[e] + (1.f - b1) * g;
+        const float vv = b2 * v[e] + (1.f - b2) * g * g;
+        m[e] = mm;
+        v[e] = vv;
+        const float p = param[e] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+        param[e] = p;
+        if (pb) pb[e] = f32_to_bf16(p);
+    }
+}
+
+__global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = f32_to_bf16(x[e]);
+}
+
+int grid_for(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return (int)(b < 16384 ? (b > 0 ? b : 1) : 16384);
+}
+
+int done() { return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE; }
+
+bool aligned8(const void *p) { return ((uintptr_t)p & 7) == 0; }
+
+int64_t positions(int nb, int d, int h, int w) { return (int64_t)nb * d * h * w; }
+
+bool dims_ok(int nb, int d, int h, int w) { return nb > 0 && d > 0 && h > 0 && w > 0; }
+
+}  // namespace
+
+extern "C" {
+
+int nn_conv3d_fwd(const uint16_t *x, int32_t ldx, const uint16_t *w, const float *bias, void *y, int32_t ldy,
+                  int32_t y_fp32, int32_t relu, int32_t nb, int32_t d, int32_t h, int32_t w_, int32_t ci, int32_t co,
+                  void *stream) {
+    if (!x || !w || !y || !dims_ok(nb, d, h, w_) || ci <= 0 || co <= 0 || ci % 16 || co % 16 || ldx < ci ||
+        ldy < co || ldx % 4 || ldy % 4 || !aligned8(x) || !aligned8(w) || (y_fp32 ? ((uintptr_t)y & 15) : !aligned8(y)))
+        return LBM_EINVAL;
+    const int64_t P = positions(nb, d, h, w_);
+    const dim3 grid((unsigned)((P + 255) / 256), (unsigned)(co / 16));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (y_fp32)
+        hipLaunchKernelGGL(conv3d_kernel<true>, grid, dim3(256), 0, s, x, ldx, w, bias, y, ldy, relu, nb, d, h, w_, ci, co);
+    else
+        hipLaunchKernelGGL(conv3d_kernel<false>, grid, dim3(256), 0, s, x, ldx, w, bias, y, ldy, relu, nb, d, h, w_, ci,
+                           co);
+    return done();
+}
+
+int nn_weights_flip(const uint16_t *w, uint16_t *wt, int32_t ci, int32_t co, void *stream) {
+    if (!w || !wt || ci <= 0 || co <= 0) return LBM_EINVAL;
+    hipLaunchKernelGGL(flip_kernel, dim3(grid_for(27LL * ci * co)), dim3(256), 0, static_cast<hipStream_t>(stream), w,
+                       wt, ci, co);
+    return done();
+}
+
+int64_t nn_bwd_weight_work(int32_t nb, int32_t d, int32_t h, int32_t w_, int32_t ci, int32_t co) {
+    if (!dims_ok(nb, d, h, w_) || ci <= 0 || co <= 0) return -1;
+    const int64_t nch = (positions(nb, d, h, w_) + kChunk - 1) / kChunk;
+    return nch * 27 * (int64_t)co * ci;   // the bias partials (nch x co) fit in the same space
+}
+
+int nn_conv3d_bwd_weight(const uint16_t *x, int32_t ldx, const uint16_t *dy, int32_t lddy, float *dw, float *db,
+                         float *work, int64_t work_floats, int32_t nb, int32_t d, int32_t h, int32_t w_, int32_t ci,
+                         int32_t co, void *stream) {
+    if (!x || !dy || !dw || !db || !work || !dims_ok(nb, d, h, w_) || ci <= 0 || co <= 0 || ci % 16 || co % 16 ||
+        co > 1024 || ldx < ci || lddy < co)
+        return LBM_EINVAL;
+    if (work_floats < nn_bwd_weight_work(nb, d, h, w_, ci, co)) return LBM_EINVAL;
+    const int64_t P = positions(nb, d, h, w_);
+    const int nch = (int)((P + kChunk - 1) / kChunk);
+    const int ntiles = 27 * (co / 16) * (ci / 16);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(bwd_weight_kernel, dim3(nch, (ntiles + 3) / 4), dim3(256), 0, s, x, ldx, dy, lddy, work, nb, d,
+                       h, w_, ci, co, ntiles);
+    const int64_t n = 27LL * co * ci;
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(grid_for(n)), dim3(256), 0, s, work, nch, n, dw);
+    hipLaunchKernelGGL(bwd_bias_kernel, dim3(nch), dim3(co), 0, s, dy, lddy, work, P, co);
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(grid_for(co)), dim3(256), 0, s, work, nch, (int64_t)co, db);
+    return done();
+}
+
+int nn_relu_bwd_cast(const float *dy, int32_t lddy, const uint16_t *y, int32_t ldy, uint16_t *out, int32_t ldo,
+                     int64_t p, int32_t c, int32_t relu, void *stream) {
+    if (!dy || !out || (relu && !y) || p <= 0 || c <= 0) return LBM_EINVAL;
+    hipLaunchKernelGGL(relu_bwd_cast_kernel, dim3(grid_for(p * c)), dim3(256), 0, static_cast<hipStream_t>(stream), dy,
+                       lddy, y, ldy, out, ldo, p, c, relu);
+    return done();
+}
+
+int nn_pool2_fwd(const uint16_t *x, int32_t ldx, uint16_t *y, int32_t ldy, int32_t nb, int32_t d, int32_t h,
+                 int32_t w_, int32_t c, void *stream) {
+    if (!x || !y || !dims_ok(nb, d, h, w_) || d % 2 || h % 2 || w_ % 2 || c <= 0) return LBM_EINVAL;
+    const int64_t Pc = positions(nb, d / 2, h / 2, w_ / 2);
+    hipLaunchKernelGGL(pool2_fwd_kernel, dim3(grid_for(Pc * c)), dim3(256), 0, static_cast<hipStream_t>(stream), x, ldx,
+                       y, ldy, Pc, d / 2, h / 2, w_ / 2, c);
+    return done();
+}
+
+int nn_pool2_bwd(const float *dy, int32_t lddy, float *dx, int32_t lddx, int32_t accumulate, int32_t nb, int32_t d,
+                 int32_t h, int32_t w_, int32_t c, void *stream) {
+    if (!dy || !dx || !dims_ok(nb, d, h, w_) || d % 2 || h % 2 || w_ % 2 || c <= 0) return LBM_EINVAL;
+    const int64_t Pc = positions(nb, d / 2, h / 2, w_ / 2);
+    hipLaunchKernelGGL(pool2_bwd_kernel, dim3(grid_for(Pc * c)), dim3(256), 0, static_cast<hipStream_t>(stream), dy,
+                       lddy, dx, lddx, accumulate, Pc, d / 2, h / 2, w_ / 2, c);
+    return done();
+}
+
+int nn_up2_fwd(const uint16_t *x, int32_t ldx, uint16_t *y, int32_t ldy, int32_t nb, int32_t d, int32_t h, int32_t w_,
+               int32_t c, void *stream) {
+    if (!x || !y || !dims_ok(nb, d, h, w_) || c <= 0) return LBM_EINVAL;
+    const int64_t Pc = positions(nb, d, h, w_);
+    hipLaunchKernelGGL(up2_fwd_kernel, dim3(grid_for(Pc * c)), dim3(256), 0, static_cast<hipStream_t>(stream), x, ldx, y,
+                       ldy, Pc, d, h, w_, c);
+    return done();
+}
+
+int nn_up2_bwd(const float *dy, int32_t lddy, float *dx, int32_t lddx, int32_t nb, int32_t d, int32_t h, int32_t w_,
+               int32_t c, void *stream) {
+    if (!dy || !dx || !dims_ok(nb, d, h, w_) || c <= 0) return LBM_EINVAL;
+    const int64_t Pc = positions(nb, d, h, w_);
+    hipLaunchKernelGGL(up2_bwd_kernel, dim3(grid_for(Pc * c)), dim3(256), 0, static_cast<hipStream_t>(stream), dy, lddy,
+                       dx, lddx, Pc, d, h, w_, c);
+    return done();
+}
+
+int nn_mse(const float *pred, int32_t ldp, const float *target, int32_t ldt, const float *cw, float *dpred,
+           int32_t lddp, double *loss, int64_t p, int32_t c, void *stream) {
+    if (!pred || !target || !cw || !dpred || !loss || p <= 0 || c <= 0) return LBM_EINVAL;
+    // the partial sums go to the loss slot's neighbours: loss[1 .. 256]
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(mse_kernel, dim3(256), dim3(256), 0, s, pred, ldp, target, ldt, cw, dpred, lddp, loss + 1, p, c);
+    hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(64), 0, s, loss + 1, 256, p, loss);
+    return done();
+}
+
+int nn_adam(float *param, const float *grad, float *m, float *v, uint16_t *param_bf16, int64_t n, float lr, float b1,
+            float b2, float eps, int32_t t, void *stream) {
+    if (!param || !grad || !m || !v || n <= 0 || t < 1) return LBM_EINVAL;
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), param, grad, m, v,
+                       param_bf16, n, lr, b1, b2, eps, c1, c2);
+    return done();
+}
+
+int nn_to_bf16(const float *x, uint16_t *y, int64_t n, void *stream) {
+    if (!x || !y || n <= 0) return LBM_EINVAL;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), x, y, n);
+    return done();
+}
+
+}  // extern "C"

@@ -299,3 +299,64 @@ def ensemble_case(count: int = 64, seed: int = 11, nu_min: float = 0.0017, g: fl
                     "tau": (nu_min / T0 + 0.5, nu_min * ratio / T0 + 0.5), "G": -3.0 * Gw,
                     "g": (0.0, 0.0, g), "rho_s": rho_s, "ratio": ratio, "theta_deg": math.degrees(theta)})
     return out
+
+
+def boolean_spheres(n: int, radius: float, porosity: float, seed: int) -> np.ndarray:
+    """Centres of independently placed spheres (overlaps allowed: the Boolean
+    model of a porous medium) in a periodic cube of edge n.  Their count is
+    the one whose expected pore fraction exp(-count v / n^3) equals the
+    requested porosity (v the sphere volume)."""
+    vol = 4.0 / 3.0 * math.pi * radius ** 3
+    count = max(1, int(round(-math.log(porosity) * n ** 3 / vol)))
+    return uniform(seed, 3 * count).reshape(count, 3) * n
+
+
+def subvolume_case(n: int, seed: int, radius_range=(6.0, 16.0), porosity_range=(0.3, 0.5),
+                   drop_radius: float = 4.0, fraction_range=(0.01, 0.05), minority: float = 0.03,
+                   interface_width: float = 1.5):
+    """A packed-sphere subvolume for the warm-start surrogate: sphere radius
+    and porosity drawn uniformly from the given ranges (Boolean model, so the
+    low porosities are reachable), droplets of component A of `drop_radius`
+    filling a drawn fraction of the pore space, tanh interfaces of the given
+    width.  Returns (solid, rho_A, rho_B, info)."""
+    r = uniform(seed, 3, offset=1 << 40)
+    radius = radius_range[0] + (radius_range[1] - radius_range[0]) * r[0]
+    porosity = porosity_range[0] + (porosity_range[1] - porosity_range[0]) * r[1]
+    frac = fraction_range[0] + (fraction_range[1] - fraction_range[0]) * r[2]
+    shape = (n, n, n)
+    centers = boolean_spheres(n, radius, porosity, seed)
+    drops, solid = pore_droplets(shape, centers, radius, drop_radius, frac, seed + 1, margin=0.5)
+    phi = np.zeros(shape)
+    if len(drops):
+        from scipy.spatial import cKDTree
+        z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+        pts = np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(np.float64)
+        d, _ = cKDTree(np.mod(drops, n), boxsize=n).query(pts)
+        phi = (0.5 * (1.0 - np.tanh((d - drop_radius) / interface_width))).reshape(shape)
+    rA = minority + (1.0 - minority) * phi
+    rB = minority + (1.0 - minority) * (1.0 - phi)
+    rA[solid == 1] = 0.0
+    rB[solid == 1] = 0.0
+    info = {"radius": float(radius), "porosity": float((solid == 0).mean()), "target_porosity": float(porosity),
+            "droplets": int(len(drops)), "drop_fraction": float(frac)}
+    return solid, rA, rB, info
+
+
+def mixture_case(n: int, seed: int, radius_range=(6.0, 16.0), porosity_range=(0.3, 0.5),
+                 fraction_range=(0.1, 0.9), total: float = 1.0):
+    """A packed-sphere subvolume (Boolean model, radius and porosity drawn
+    uniformly from the ranges) filled with a uniform mixture: component A
+    holds a drawn fraction c of the total density, B the rest.  Below the
+    demixing coupling the mixture stays miscible and the flow it carries has
+    a steady state.  Returns (solid, rho_A, rho_B, info)."""
+    r = uniform(seed, 3, offset=1 << 41)
+    radius = radius_range[0] + (radius_range[1] - radius_range[0]) * r[0]
+    porosity = porosity_range[0] + (porosity_range[1] - porosity_range[0]) * r[1]
+    c = fraction_range[0] + (fraction_range[1] - fraction_range[0]) * r[2]
+    shape = (n, n, n)
+    solid = voxelize_spheres(shape, boolean_spheres(n, radius, porosity, seed), radius)
+    rA = np.where(solid == 1, 0.0, c * total)
+    rB = np.where(solid == 1, 0.0, (1.0 - c) * total)
+    info = {"radius": float(radius), "porosity": float((solid == 0).mean()), "target_porosity": float(porosity),
+            "fraction": float(c)}
+    return solid, rA, rB, info

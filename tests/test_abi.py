@@ -49,6 +49,31 @@ def test_library_exports_every_declared_symbol(lbm):
     assert set(names) <= exported
 
 
+def test_library_exports_the_surrogate_kernels(lbm):
+    from paper_1711_03254_amd import nn
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "lbm_nn.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(nn_[a-z0-9_]+)\s*\(", text)))
+    assert set(names) == set(nn.NN_EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    assert set(names) <= set(re.findall(r"\bT (nn_\w+)", out))
+    nn.load()   # argument types bind to every symbol
+
+
+def test_surrogate_calls_reject_bad_sizes_on_the_host(lbm):
+    """Size and alignment checks happen before anything is enqueued (no
+    device memory is touched: the pointers are never dereferenced)."""
+    import ctypes
+    from paper_1711_03254_amd import nn
+    lib = nn.load()
+    p = ctypes.c_void_p(1 << 20)
+    assert lib.nn_conv3d_fwd(p, 16, p, None, p, 16, 1, 0, 1, 4, 4, 4, 8, 16, None) == lbm.LBM_EINVAL   # ci % 16
+    assert lib.nn_conv3d_fwd(p, 18, p, None, p, 16, 1, 0, 1, 4, 4, 4, 16, 16, None) == lbm.LBM_EINVAL  # ldx % 4
+    assert lib.nn_pool2_fwd(p, 16, p, 16, 1, 3, 4, 4, 16, None) == lbm.LBM_EINVAL                      # odd extent
+    assert lib.nn_bwd_weight_work(1, 4, 4, 4, 16, 16) == 27 * 16 * 16
+    assert lib.nn_conv3d_bwd_weight(p, 16, p, 16, p, p, p, 10, 1, 4, 4, 4, 16, 16, None) == lbm.LBM_EINVAL
+    assert lib.nn_adam(p, p, p, p, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == lbm.LBM_EINVAL       # t < 1
+
+
 def test_struct_layout_matches_c(lbm, tmp_path):
     prog = tmp_path / "layout.c"
     fields_p = [f for f, _ in lbm.lbm_params._fields_]
