@@ -116,6 +116,47 @@ def cpu_baseline(solid, rA, rB, phys, steps=3):
             "sample": f"the full {n}^3 workload, {steps} steps of the FP64 oracle ({dt:.1f} s)"}
 
 
+def ensemble(lbm, torch, steps, warmup):
+    """The batched ensemble: 64 ducts of uneven sizes stepped by one
+    graph-replayed launch per step, against the same domains stepped one
+    launch each.  FP32; MLUPS over all fluid sites; wall clock with the
+    device synchronized on both sides (the batch runs on its own stream)."""
+    from paper_1711_03254_amd import inputs
+    doms = inputs.ensemble_case(64)
+    stream = torch.cuda.Stream()
+    ctxs = []
+    for d in doms:
+        nz, ny, nx = d["shape"]
+        ctxs.append(lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.LBM_FP32, solid=d["solid"],
+                                            rho_init=(d["rho_A"], d["rho_B"]), tau=d["tau"], G=d["G"], g=d["g"],
+                                            rho_s=d["rho_s"], stream=stream, tile=(64, 4))))
+    nf = sum(lbm.lbm_info(c)["n_fluid"] for c in ctxs)
+    for c in ctxs:
+        lbm.lbm_step(c, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in ctxs:
+        lbm.lbm_step(c, steps)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    b = lbm.lbm_batch_create(ctxs)
+    lbm.lbm_batch_step(b, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lbm.lbm_batch_step(b, steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    lbm.lbm_batch_free(b)
+    for c in ctxs:
+        lbm.lbm_free(c)
+    out = {"domains": len(doms), "n_fluid": nf, "steps": steps}
+    for name, t in (("batched", t_batch), ("one_launch_per_domain", t_single)):
+        mlups = nf * steps / t / 1e6
+        out[name] = {"ms_per_step": round(t / steps * 1e3, 4), "mlups": round(mlups, 1),
+                     "hbm_frac": round(mlups * 1e6 * 304 / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 WEIGHTS = os.path.join(ROOT, "paper_1711_03254_amd", "weights", "surrogate_mixture_b32.npz")
 
 
@@ -162,6 +203,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--G", type=float, default=-4.2)
     ap.add_argument("--interface-width", type=float, default=1.5)
+    ap.add_argument("--no-ensemble", dest="ensemble", action="store_false",
+                    help="skip the batched 64-domain ensemble")
     ap.add_argument("--no-warm-start", dest="warm_start", action="store_false",
                     help="skip the cold / warm time-to-steady-state comparison")
     ap.add_argument("--no-all-fluid", dest="all_fluid", action="store_false",
@@ -211,6 +254,10 @@ def main():
             r = time_precision(lbm, torch, prec, zero, dA, dB, phys_af, max(50, args.steps // 2), args.warmup, 0)
             allf[prec] = {k: r[k] for k in ("kernel_ms", "kernel_mlups", "algorithmic_GBs", "hbm_frac")}
             print(f"# all-fluid {prec}: {json.dumps(allf[prec])}", file=sys.stderr, flush=True)
+    ens = None
+    if args.ensemble:
+        ens = ensemble(lbm, torch, max(20, args.steps // 5), 4)
+        print(f"# ensemble: {json.dumps(ens)}", file=sys.stderr, flush=True)
     ws_res = None
     if args.warm_start:
         ws_res = warm_start(lbm)
@@ -258,6 +305,7 @@ def main():
         "cpu_baseline": cpu,
         "all_fluid": {k: {kk: round(v, 4) for kk, v in r.items()} for k, r in allf.items()},
         "warm_start": ws_res,
+        "ensemble": ens,
         "precisions": {k: {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()}
                        for k, r in res.items()},
     }
