@@ -22,6 +22,8 @@ struct lbm_ctx {
     int cur = 0;
     uint32_t *links = nullptr;   // per-site link mask (set-up and exchange kernels)
     int32_t *idx = nullptr;      // compact population index per site, -1 where solid
+    int32_t *wstart = nullptr;   // work lists of the step: bounds per tile column and plane
+    uint16_t *wpos = nullptr;    // work list entries (tile positions of fluid sites)
     double *partials = nullptr;
     double *red_dev = nullptr;
     double *red_host = nullptr;   // pinned
@@ -133,6 +135,8 @@ lbm::StepLaunch make_launch(const lbm_ctx *c, const void *src, void *dst) {
     L.src = src;
     L.dst = dst;
     L.idx = c->idx;
+    L.wstart = c->wstart;
+    L.wpos = c->wpos;
     L.nx = p.nx; L.ny = p.ny; L.nz = p.nz;
     L.plane = c->plane;
     L.tile_x = c->tile_x; L.tile_y = c->tile_y; L.zchunk = c->zchunk;
@@ -270,12 +274,37 @@ int64_t build_index(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty
     return k;
 }
 
+// Work lists of the step: per tile column and z plane, the tile positions
+// (ly tx + lx) of the plane's fluid sites in storage order.  In tiles that
+// reach past the lattice edge, the positions beyond it stand for their
+// periodic images (pulled for their densities, not stored).
+void build_work(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty, std::vector<int32_t> &wstart,
+                std::vector<uint16_t> &wpos) {
+    const int ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty;
+    wstart.assign((size_t)ntx * nty * (nz + 1), 0);
+    wpos.clear();
+    for (int by = 0; by < nty; ++by)
+        for (int bx = 0; bx < ntx; ++bx) {
+            const size_t col = (size_t)(by * ntx + bx) * (nz + 1);
+            for (int z = 0; z < nz; ++z) {
+                wstart[col + z] = (int32_t)wpos.size();
+                for (int ly = 0; ly < ty; ++ly)
+                    for (int lx = 0; lx < tx; ++lx) {
+                        const int x = (bx * tx + lx) % nx, y = (by * ty + ly) % ny;
+                        const int64_t s = x + (int64_t)nx * (y + (int64_t)ny * z);
+                        if (!solid || !solid[s]) wpos.push_back((uint16_t)(ly * tx + lx));
+                    }
+            }
+            wstart[col + nz] = (int32_t)wpos.size();
+        }
+}
+
 void release(lbm_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (void *q : {c->f[0], c->f[1], (void *)c->links, (void *)c->idx, (void *)c->partials, (void *)c->red_dev,
-                    (void *)c->stage})
+    for (void *q : {c->f[0], c->f[1], (void *)c->links, (void *)c->idx, (void *)c->wstart, (void *)c->wpos,
+                    (void *)c->partials, (void *)c->red_dev, (void *)c->stage})
         if (q) (void)hipFree(q);
     if (c->red_host) (void)hipHostFree(c->red_host);
     for (int k = 0; k < 2; ++k) {
@@ -380,6 +409,17 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         return bail(fail(c, LBM_ENOMEM, "cannot allocate the link mask, index or reduction buffers"));
     if (hipMemcpy(c->idx, idx_h.data(), sizeof(int32_t) * c->N, hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(c, LBM_EDEVICE, "cannot upload the site index"));
+    {
+        std::vector<int32_t> ws;
+        std::vector<uint16_t> wp;
+        build_work(p.solid ? solid_h.data() : nullptr, p.nx, p.ny, p.nz, c->tile_x, c->tile_y, ws, wp);
+        if (hipMalloc(&c->wstart, sizeof(int32_t) * ws.size()) != hipSuccess ||
+            hipMalloc(&c->wpos, sizeof(uint16_t) * std::max<size_t>(wp.size(), 1)) != hipSuccess)
+            return bail(fail(c, LBM_ENOMEM, "cannot allocate the work lists"));
+        if (hipMemcpy(c->wstart, ws.data(), sizeof(int32_t) * ws.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->wpos, wp.data(), sizeof(uint16_t) * wp.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(c, LBM_EDEVICE, "cannot upload the work lists"));
+    }
 
     // Solid mask -> link mask.
     uint8_t *solid_d = nullptr;

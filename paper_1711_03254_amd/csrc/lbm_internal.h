@@ -29,6 +29,8 @@ struct StepLaunch {
     const void *src;
     void *dst;
     const int32_t *idx;     // compact population index of each lattice site, -1 where solid
+    const int32_t *wstart;  // work list bounds: per tile column (ty ntx + tx) nz + 1 entries
+    const uint16_t *wpos;   // work list entries: tile positions ly tile_x + lx of fluid sites
     int nx, ny, nz;
     int64_t plane;          // sites per direction plane (fluid sites plus padding); a plane holds
                             // the pairs (component 1, component 2) of those sites

@@ -96,6 +96,8 @@ struct KArgs {
     const S *src;
     S *dst;
     const int32_t *idx;     // compact index of each lattice site, -1 where solid
+    const int32_t *wstart;  // work list bounds per tile column and plane
+    const uint16_t *wpos;   // work list entries: tile positions of the fluid sites
     int nx, ny, nz, ntx, nty, zchunk;
     uint32_t plane_bytes;   // bytes of one direction's plane of component pairs
     C tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
@@ -352,11 +354,13 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
 // the domain described by a; partial sums (MODE_CHECK / MODE_MOMENTS) go to
 // a.partials[slot].
 //
-// Per plane: the tile's and the ring's pulls are issued together; the
-// interior keeps only the ten moments per component of its site (the
-// regularized collision rebuilds f* from them and the force), the ring only
-// its densities.  The collision of a plane waits for the next plane's
-// densities (one barrier per plane).
+// Per plane: the tile's fluid sites are taken from the plane's work list
+// (lane j gets the j-th fluid site, so lanes are busy only where there is
+// fluid and whole waves idle on solid), the ring sites by the highest
+// lanes.  Their pulls are issued together; the interior keeps only the ten
+// moments per component of its site (the regularized collision rebuilds f*
+// from them and the force), the ring only its densities.  The collision of
+// a plane waits for the next plane's densities (one barrier per plane).
 template <typename S, int TX, int TY, int MODE>
 __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     using C = typename Codec<S>::C;
@@ -382,22 +386,35 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     const int z1 = min(z0 + a.zchunk, a.nz);
 
     const int tid = threadIdx.x;
-    const int lx = tid % TX, ly = tid / TX;
-    const int gx = tx * TX + lx, gy = ty * TY + ly;
-    const bool inside = gx < a.nx && gy < a.ny;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
     const uint32_t pb = a.plane_bytes;
-    const uint32_t site_xy = (uint32_t)(gx % nx) + (uint32_t)nx * (uint32_t)(gy % ny);
 
-    // This thread's ring site, in density-tile coordinates (rr, rc).
-    const bool has_ring = tid < NR;
-    const bool ring_wave = (tid & ~63) < NR;   // the wave holds at least one ring site
+    // This thread's ring site, in density-tile coordinates (rr, rc): ring
+    // index rt counts down from the last thread, so that the ring falls on
+    // the waves the work list leaves idle first.
+    const int rt = NT - 1 - tid;
+    const bool has_ring = rt < NR;
+    const bool ring_wave = NT - 64 * (tid / 64 + 1) < NR;   // the wave holds at least one ring site
     int rr = 0, rc = 0;
-    if (tid < RW) { rr = 0; rc = tid; }
-    else if (tid < 2 * RW) { rr = RH - 1; rc = tid - RW; }
-    else if (tid < 2 * RW + TY) { rr = 1 + tid - 2 * RW; rc = 0; }
-    else if (tid < NR) { rr = 1 + tid - 2 * RW - TY; rc = RW - 1; }
+    if (rt < RW) { rr = 0; rc = rt; }
+    else if (rt < 2 * RW) { rr = RH - 1; rc = rt - RW; }
+    else if (rt < 2 * RW + TY) { rr = 1 + rt - 2 * RW; rc = 0; }
+    else if (rt < NR) { rr = 1 + rt - 2 * RW - TY; rc = RW - 1; }
+    // The site this thread owns for the solid test of the density tile.
+    const int tly = tid / TX, tlx = tid % TX;
+
+    // Work lists: per tile column and plane z, entries wstart[col (nz + 1) + z]
+    // to wstart[... + z + 1] of wpos, the tile positions (ly TX + lx) of the
+    // plane's fluid sites in storage order (positions beyond the lattice edge
+    // stand for their periodic images and are pulled but not stored).
+    const int32_t *ws = a.wstart + (size_t)(ty * a.ntx + tx) * (nz + 1);
+    auto fetch_work = [&](int zq, int &cnt, int &pos) {
+        const int zz = wrap(zq, nz);
+        const int w0 = ws[zz];
+        cnt = ws[zz + 1] - w0;
+        pos = tid < cnt ? (int)a.wpos[w0 + tid] : 0;
+    };
 
     // The index-tile entries this thread stages: their lattice (x, y).
     uint32_t exy[NE];
@@ -455,8 +472,11 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     Moments<C> mc[2], mn[2];     // moments of the plane to collide / of the next plane
 #pragma unroll
     for (int d = 0; d < 2; ++d) mn[d] = Moments<C>{C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
+    // this lane's work-list site of the plane to collide (c) / of the next plane (n)
     bool fluid_c = false, fluid_n = false;
-    int kc = 0, kn = 0;          // byte offsets of this site in the plane to collide / the next plane
+    int kc = 0, kn = 0;          // byte offsets of its populations within a plane
+    int pc = 0, pn = 0;          // tile positions ly TX + lx
+    int wcnt = 0, wpos = 0;      // work list of the plane to pull next (prefetched)
     const C ref0 = a.ref0, ref1 = a.ref1;
 
     // Pulls plane zw (z0 - 1 <= zw <= z1, unwrapped) into density slot
@@ -465,19 +485,23 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     auto load_plane = [&](int zw, int lslot, bool keep) {
         const int qw = zw - z0 + 2;
         const int qm = (qw + 4) % 5, q0 = qw % 5, qp = (qw + 1) % 5;
-        const int si = kid[q0][ly + 2][lx + 2];
+        const bool fi = tid < wcnt;
+        const int lx = wpos % TX, ly = wpos / TX;
+        const int si = fi ? kid[q0][ly + 2][lx + 2] : -1;
         const int sr = has_ring ? kid[q0][rr + 1][rc + 1] : -1;
-        const bool fi = si >= 0, fr = sr >= 0;
+        const bool fr = sr >= 0;
+        const int pos_here = wpos;
         int vnext[NE];
         fetch_idx(zw + 2, vnext);
+        fetch_work(zw + 1, wcnt, wpos);
         S ri[2][19], rg[2][19];
         // All of the plane's loads are issued before any is consumed: one
-        // memory round trip per plane.  Lanes without a pull (solid sites,
-        // no ring site) issue no load and use none of these values.
+        // memory round trip per plane.  Lanes without a pull (past the work
+        // list, no fluid ring site) issue no load and use none of these values.
         if (fi) issue(ly + 2, lx + 2, qm, q0, qp, (uint32_t)si, ri);
         if (fr) issue(rr + 1, rc + 1, qm, q0, qp, (uint32_t)sr, rg);
         __builtin_amdgcn_sched_barrier(0);
-        C r0 = a.wall0, r1 = a.wall1;
+        C r0 = C(0), r1 = C(0);
         if (fi) {
             if (keep) {
                 mn[0] = moments_of<S>(ri[0], ref0);
@@ -491,8 +515,15 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
         }
         fluid_n = fi;
         kn = si;
-        psi0[lslot][ly + 1][lx + 1] = r0;
-        psi1[lslot][ly + 1][lx + 1] = r1;
+        pn = pos_here;
+        if (fi) {
+            psi0[lslot][ly + 1][lx + 1] = r0;
+            psi1[lslot][ly + 1][lx + 1] = r1;
+        }
+        if (kid[q0][tly + 2][tlx + 2] < 0) {   // solid site of the tile: the wall densities
+            psi0[lslot][tly + 1][tlx + 1] = a.wall0;
+            psi1[lslot][tly + 1][tlx + 1] = a.wall1;
+        }
         if (ring_wave) {
             C q0v = a.wall0, q1v = a.wall1;
             if (fr) {
@@ -517,6 +548,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
             store_idx(q, v);
         }
     }
+    fetch_work(z0 - 1, wcnt, wpos);
     __syncthreads();
     load_plane(z0 - 1, 0, false);
     __syncthreads();
@@ -525,6 +557,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     mc[1] = mn[1];
     fluid_c = fluid_n;
     kc = kn;
+    pc = pn;
     __syncthreads();
 
     const __amdgpu_buffer_rsrc_t dstA = half_rsrc(a.dst, 0, pb), dstB = half_rsrc(a.dst, 1, pb);
@@ -534,6 +567,8 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
         load_plane(z + 1, sp, true);
         __syncthreads();
 
+        const int lx = pc % TX, ly = pc / TX;
+        const bool inside = tx * TX + lx < nx && ty * TY + ly < ny;   // not a periodic image
         if (inside && fluid_c) {
             const C rho[2] = {mc[0].r, mc[1].r};
 
@@ -580,7 +615,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                 acc[5] += ok ? 0.0 : 1.0;
             }
             if constexpr (MODE == MODE_MOMENTS) {
-                const uint32_t s = site_xy + (uint32_t)z * nxy;
+                const uint32_t s = (uint32_t)(tx * TX + lx) + (uint32_t)nx * (uint32_t)(ty * TY + ly) + (uint32_t)z * nxy;
                 if (a.out_rho0) a.out_rho0[s] = (double)rho[0];
                 if (a.out_rho1) a.out_rho1[s] = (double)rho[1];
                 if (a.out_u) {
@@ -636,6 +671,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
         mc[1] = mn[1];
         fluid_c = fluid_n;
         kc = kn;
+        pc = pn;
     }
 
     if constexpr (MODE == MODE_CHECK || MODE == MODE_MOMENTS) {
@@ -846,6 +882,8 @@ KArgs<S> make_kargs(const StepLaunch &L) {
     a.src = static_cast<const S *>(L.src);
     a.dst = static_cast<S *>(L.dst);
     a.idx = L.idx;
+    a.wstart = L.wstart;
+    a.wpos = L.wpos;
     a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
     a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk;
     a.plane_bytes = (uint32_t)(L.plane * 2 * (int64_t)sizeof(S));   // a plane of component pairs
