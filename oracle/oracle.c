@@ -106,7 +106,8 @@ typedef struct {
     int32_t nx, ny, nz;
     int32_t eq_kind;     /* 0: Eq. (3) as printed; 1: with the second-order terms */
     int32_t force_kind;  /* 0: forcing with its second-order part (default); 1: first order only */
-    int32_t pad_;
+    int32_t wall_kind;   /* 0: wall force as Eq. (11) gives it (W1); 1: minus its share of the
+                            mixture's net wall force (W2) */
     double tau[2];       /* tau_alpha > 1/2; nu_alpha = T0 (tau_alpha - 1/2) */
     double G;            /* Eq. (7); G < 0 is repulsive */
     double g[3];         /* body acceleration */
@@ -262,19 +263,43 @@ static void field_force(const ora_params *p, const double *rho, double *F)
     int64_t N = nsites(p);
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N; ++s) {
-        for (int a = 0; a < 2; ++a) {
-            int b = 1 - a;
-            double acc[3] = {0.0, 0.0, 0.0};
-            if (!is_solid(p, s)) {
+        /* per component: the fluid-fluid part of Eq. (7) and the wall part of
+         * Eq. (11) (neighbours on solid sites carry the wall density) */
+        double ff[2][3] = {{0, 0, 0}, {0, 0, 0}}, fw[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        if (!is_solid(p, s)) {
+            for (int a = 0; a < 2; ++a) {
+                int b = 1 - a;
                 for (int i = 0; i < Q; ++i) {
                     int64_t n = shifted(p, s, CV[i][0], CV[i][1], CV[i][2]);
-                    double rho_prime = is_solid(p, n) ? wall_density(p->rho_s, b) : rho[b * N + n];
-                    for (int d = 0; d < 3; ++d) acc[d] += weight(i) * CV[i][d] * rho_prime;
+                    for (int d = 0; d < 3; ++d) {
+                        if (is_solid(p, n))
+                            fw[a][d] += weight(i) * CV[i][d] * wall_density(p->rho_s, b);
+                        else
+                            ff[a][d] += weight(i) * CV[i][d] * rho[b * N + n];
+                    }
                 }
-                for (int d = 0; d < 3; ++d)
-                    acc[d] = p->G * rho[a * N + s] * acc[d] + rho[a * N + s] * p->g[d];
+                for (int d = 0; d < 3; ++d) {
+                    ff[a][d] *= p->G * rho[a * N + s];
+                    fw[a][d] *= p->G * rho[a * N + s];
+                }
             }
-            for (int d = 0; d < 3; ++d) F[(a * 3 + d) * N + s] = acc[d];
+        }
+        for (int a = 0; a < 2; ++a) {
+            for (int d = 0; d < 3; ++d) {
+                double v = 0.0;
+                if (!is_solid(p, s)) {
+                    double wall = fw[a][d];
+                    if (p->wall_kind == 1) {
+                        /* W2: each component gives up its density share of the
+                         * mixture's net wall force, so that the walls push the
+                         * components apart but not the mixture */
+                        double rho_mix = rho[s] + rho[N + s];
+                        wall -= rho[a * N + s] / rho_mix * (fw[0][d] + fw[1][d]);
+                    }
+                    v = ff[a][d] + wall + rho[a * N + s] * p->g[d];
+                }
+                F[(a * 3 + d) * N + s] = v;
+            }
         }
     }
 }

@@ -42,7 +42,7 @@ class _Params(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("eq_kind", ctypes.c_int32),
         ("force_kind", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("wall_kind", ctypes.c_int32),
         ("tau", ctypes.c_double * 2),
         ("G", ctypes.c_double),
         ("g", ctypes.c_double * 3),
@@ -102,6 +102,7 @@ class Params:
     rho_s: float = 0.0
     eq_kind: int = 0
     force_kind: int = 0
+    wall_kind: int = 0
     solid: np.ndarray | None = None
     _keep: list = field(default_factory=list, repr=False)
 
@@ -113,6 +114,7 @@ class Params:
         s = _Params()
         s.nx, s.ny, s.nz, s.eq_kind = self.nx, self.ny, self.nz, self.eq_kind
         s.force_kind = self.force_kind
+        s.wall_kind = self.wall_kind
         s.tau[0], s.tau[1] = self.tau
         s.G = self.G
         for d in range(3):

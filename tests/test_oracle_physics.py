@@ -241,3 +241,57 @@ def test_wettability_sign(one_thread):
     assert abs(frac[0.0] - 0.5) < 1e-12
     assert frac[0.3] > frac[0.0] + 0.02
     assert frac[-0.3] < frac[0.0] - 0.02
+
+
+def _wall_case(seed, shape=(10, 14, 12), two_components=True):
+    nz, ny, nx = shape
+    solid = inputs.random_mask(shape, 0.12, seed)
+    solid[:, 0, :] = 1
+    r1 = inputs.smooth_random_density(shape, seed + 1, mean=0.6, amp=0.2)
+    r2 = inputs.smooth_random_density(shape, seed + 2, mean=0.4, amp=0.2) if two_components else np.zeros(shape)
+    r1[solid == 1] = 0
+    r2[solid == 1] = 0
+    return solid, r1, r2
+
+
+def test_momentum_balanced_wall_force_leaves_the_mixture_force_alone(ora):
+    """Reading W2 of the wall force (Section 3.3: the interaction force along
+    walls balanced between the components): each component gives up its
+    density share of the mixture's net wall force.  Then the wall potential
+    cannot change the mixture force, hence not u_F = (j + F / 2) / rho
+    (Eq. 8) of any state -- while under W1 it does -- and it still changes the
+    components' motion relative to each other."""
+    solid, r1, r2 = _wall_case(81)
+    nz, ny, nx = solid.shape
+    base = dict(tau=(0.8, 1.1), G=-2.5, g=(1e-5, 0.0, 2e-5), solid=solid)
+    f0 = ora.init(ora.Params(nx, ny, nz, **base), r1, r2)
+    u = {}
+    for wk in (0, 1):
+        for rs in (-0.3, 0.0, 0.3):
+            u[wk, rs] = ora.moments(ora.Params(nx, ny, nz, rho_s=rs, wall_kind=wk, **base), f0)[2]
+    scale = np.abs(u[0, 0.0]).max()
+    assert np.abs(u[1, 0.3] - u[1, 0.0]).max() <= 1e-13 * scale
+    assert np.abs(u[1, -0.3] - u[1, 0.0]).max() <= 1e-13 * scale
+    assert np.abs(u[0, 0.3] - u[0, 0.0]).max() > 1e-3 * scale          # W1: the walls push the mixture
+    # the relative force remains: after some steps the components differ
+    fa = ora.run(ora.Params(nx, ny, nz, rho_s=0.3, wall_kind=1, **base), f0, 20)
+    fb = ora.run(ora.Params(nx, ny, nz, rho_s=-0.3, wall_kind=1, **base), f0, 20)
+    ra, rb = ora.moments(ora.Params(nx, ny, nz, wall_kind=1, **base), fa)[0], \
+        ora.moments(ora.Params(nx, ny, nz, wall_kind=1, **base), fb)[0]
+    assert np.abs(ra - rb).max() > 1e-3
+
+
+def test_momentum_balanced_wall_force_single_component(ora):
+    """With component 2 absent, W2 removes the wall force on component 1
+    entirely (its share of the net wall force is all of it): the evolution
+    does not depend on the wall potential, bit for bit; under W1 it does."""
+    solid, r1, r2 = _wall_case(91, two_components=False)
+    nz, ny, nx = solid.shape
+    base = dict(tau=(0.9, 1.0), G=-2.5, g=(0.0, 1e-5, 0.0), solid=solid)
+    f0 = ora.init(ora.Params(nx, ny, nz, **base), r1, r2)
+    out = {}
+    for wk in (0, 1):
+        for rs in (0.0, 0.4):
+            out[wk, rs] = ora.run(ora.Params(nx, ny, nz, rho_s=rs, wall_kind=wk, **base), f0, 10)
+    assert np.array_equal(out[1, 0.4], out[1, 0.0])
+    assert not np.allclose(out[0, 0.4], out[0, 0.0], rtol=0, atol=1e-9)
