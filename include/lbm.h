@@ -91,6 +91,11 @@ typedef struct {
     int32_t tile_x, tile_y;      /* x-y tile of the step kernel (0 = library default; 64x4, 32x8,
                                     16x16, 8x32, 64x8 or 32x16) */
     int32_t zchunk;              /* z planes per block (0 = library default) */
+    int32_t wall_kind;           /* 0: the wall force of Eq. (11) as it stands (W1, default);
+                                    1: each component gives up its density share of the mixture's
+                                    net wall force, so that the walls separate the components
+                                    without pushing the mixture (W2, the momentum-balanced wall
+                                    interaction of Section 3.3) */
 } lbm_params;
 
 /* Creates a context: validates p, allocates the device state and sets the

@@ -147,7 +147,7 @@ lbm::StepLaunch make_launch(const lbm_ctx *c, const void *src, void *dst) {
     L.wall1 = p.rho_s > 0 ? p.rho_s : 0.0;    // rho^s_2 =  rho^s Theta(rho^s)
     L.ref0 = c->ref[0];
     L.ref1 = c->ref[1];
-    L.eq_kind = p.eq_kind; L.force_kind = p.force_kind;
+    L.eq_kind = p.eq_kind; L.force_kind = p.force_kind; L.wall_kind = p.wall_kind;
     L.partials = c->partials;
     return L;
 }
@@ -335,6 +335,7 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         return fail(nullptr, LBM_EINVAL, "G, g and rho_s must be finite");
     if (p.eq_kind != 0 && p.eq_kind != 1) return fail(nullptr, LBM_EINVAL, "eq_kind must be 0 or 1");
     if (p.force_kind != 0 && p.force_kind != 1) return fail(nullptr, LBM_EINVAL, "force_kind must be 0 or 1");
+    if (p.wall_kind != 0 && p.wall_kind != 1) return fail(nullptr, LBM_EINVAL, "wall_kind must be 0 or 1");
     if (p.check_every < 0) return fail(nullptr, LBM_EINVAL, "check_every must be >= 0");
     if (!(p.mass_tol >= 0) || !std::isfinite(p.rho_ref[0]) || !std::isfinite(p.rho_ref[1]))
         return fail(nullptr, LBM_EINVAL, "mass_tol must be >= 0 and rho_ref finite");

@@ -37,7 +37,7 @@ struct StepLaunch {
     int tile_x, tile_y, zchunk;
     int ntx, nty, nzc;      // tiles in x, y and chunks in z
     double tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
-    int eq_kind, force_kind;
+    int eq_kind, force_kind, wall_kind;
     double *partials;       // kPartialStride doubles per block
     double *out_rho0, *out_rho1, *out_u;  // MODE_MOMENTS outputs (N, N, 3N)
 };

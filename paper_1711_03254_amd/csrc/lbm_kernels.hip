@@ -101,7 +101,7 @@ struct KArgs {
     int nx, ny, nz, ntx, nty, zchunk;
     uint32_t plane_bytes;   // bytes of one direction's plane of component pairs
     C tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
-    int eq_kind, force_kind;
+    int eq_kind, force_kind, wall_kind;
     double *partials;
     double *out_rho0, *out_rho1, *out_u;
     int64_t n_sites;
@@ -596,6 +596,33 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
             Fx[1] = rho[1] * (a.G * n0x + a.gx);
             Fy[1] = rho[1] * (a.G * n0y + a.gy);
             Fz[1] = rho[1] * (a.G * n0z + a.gz);
+            if (a.wall_kind == 1) {
+                // Momentum-balanced walls: the wall part of the force on
+                // component a is G rho_a rho^s_b S with S = sum of w_i c_i over
+                // the solid neighbours x + c_i; each component gives up its
+                // share rho_a / rho of the sum over both components.
+                C Sx = C(-0.0), Sy = C(-0.0), Sz = C(-0.0);
+                sfor<19>([&](auto I) {
+                    constexpr int i = I;
+                    if constexpr (i > 0) {
+                        constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+                        const int q = ((z + Z) - z0 + 2) % 5;   // index slot of plane z + Z
+                        const C sol = kid[q][ly + 2 + Y][lx + 2 + X] < 0 ? C(w_of(i)) : C(0);
+                        if constexpr (X != 0) Sx += C(X) * sol;
+                        if constexpr (Y != 0) Sy += C(Y) * sol;
+                        if constexpr (Z != 0) Sz += C(Z) * sol;
+                    }
+                });
+                const C net = a.G * (rho[0] * a.wall1 + rho[1] * a.wall0);
+                const C inv_t = recip(rho[0] + rho[1]);
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    const C share = rho[d] * inv_t * net;
+                    Fx[d] -= share * Sx;
+                    Fy[d] -= share * Sy;
+                    Fz[d] -= share * Sz;
+                }
+            }
 
             // Eq. (8): u_F = (j_1 + j_2 + F / 2) / rho.
             const C rho_t = rho[0] + rho[1];
@@ -890,7 +917,7 @@ KArgs<S> make_kargs(const StepLaunch &L) {
     a.tau0 = (C)L.tau0; a.tau1 = (C)L.tau1; a.G = (C)L.G;
     a.gx = (C)L.gx; a.gy = (C)L.gy; a.gz = (C)L.gz;
     a.wall0 = (C)L.wall0; a.wall1 = (C)L.wall1; a.ref0 = (C)L.ref0; a.ref1 = (C)L.ref1;
-    a.eq_kind = L.eq_kind; a.force_kind = L.force_kind;
+    a.eq_kind = L.eq_kind; a.force_kind = L.force_kind; a.wall_kind = L.wall_kind;
     a.partials = L.partials;
     a.out_rho0 = L.out_rho0; a.out_rho1 = L.out_rho1; a.out_u = L.out_u;
     a.n_sites = (int64_t)L.nx * L.ny * L.nz;

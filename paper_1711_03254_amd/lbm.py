@@ -52,6 +52,7 @@ class lbm_params(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
         ("zchunk", ctypes.c_int32),
+        ("wall_kind", ctypes.c_int32),
     ]
 
 
@@ -139,6 +140,7 @@ class Params:
     rho_s: float = 0.0
     eq_kind: int = 0
     force_kind: int = 0
+    wall_kind: int = 0
     check_every: int = 0
     mass_tol: float = 0.0
     rho_ref: tuple = (0.0, 0.0)
@@ -183,6 +185,7 @@ def lbm_init(p: Params) -> Context:
         s.g[d] = p.g[d]
     s.rho_s = p.rho_s
     s.eq_kind, s.force_kind, s.check_every = p.eq_kind, p.force_kind, p.check_every
+    s.wall_kind = p.wall_kind
     s.mass_tol = p.mass_tol
     s.rho_ref[0], s.rho_ref[1] = p.rho_ref
     flags = set()

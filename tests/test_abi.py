@@ -105,6 +105,7 @@ def test_struct_layout_matches_c(lbm, tmp_path):
     (dict(tau=(1.0, 0.3)), "tau"),
     (dict(prec=7), "precision"),
     (dict(eq_kind=2), "eq_kind"),
+    (dict(wall_kind=3), "wall_kind"),
     (dict(force_kind=-1), "force_kind"),
     (dict(tile=(48, 4)), "tile"),
     (dict(nx=0), "dimensions"),

@@ -96,6 +96,38 @@ def test_one_step_from_random_state(lbm, ora, prec, tile, eq_kind, force_kind):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("tile", [(64, 4), (8, 32)])
+@pytest.mark.parametrize("rho_s", [0.3, -0.25])
+def test_momentum_balanced_walls(lbm, ora, prec, tile, rho_s):
+    """The momentum-balanced wall force (wall_kind 1) against the oracle:
+    one step from a random state with walls, and 40 steps of a smooth
+    two-component state (the force terms then matter beyond rounding)."""
+    solid, f0 = ragged_case(seed=17)
+    shape = f0.shape[2:]
+    nz, ny, nx = shape
+    kw = dict(PHYS, rho_s=rho_s, wall_kind=1)
+    ctx = gpu_ctx(lbm, shape, prec, solid, tile=tile, zchunk=7, **kw)
+    lbm.lbm_set_populations(ctx, f0)
+    lbm.lbm_step(ctx, 1)
+    p = ora.Params(nx, ny, nz, solid=solid, **kw)
+    dev1 = nmax(lbm.lbm_get_populations(ctx), ora.step(p, f0))
+    r1 = inputs.smooth_random_density(shape, 18, mean=0.6, amp=0.25)
+    r2 = 1.0 - r1
+    r1[solid == 1] = 0
+    r2[solid == 1] = 0
+    g0 = ora.init(p, r1, r2)
+    c2 = lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(r1, r2), tile=tile,
+                                 **kw))
+    lbm.lbm_step(c2, 40)
+    m = lbm.lbm_moments(c2)
+    want = ora.moments(p, ora.run(p, g0, 40))
+    devs = [nmax(m[0], want[0]), nmax(m[1], want[1]), nmax(m[2], want[2])]
+    record("walls_w2", prec=prec, tile=list(tile), rho_s=rho_s, one_step=dev1, moments40=devs)
+    assert dev1 <= TOL[prec]
+    assert max(devs) <= (TOL[prec] if prec == "fp64" else fp32_bound(40))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_moments_and_reduce_match(lbm, ora, prec):
     solid, f0 = ragged_case(seed=11)
     shape = f0.shape[2:]
