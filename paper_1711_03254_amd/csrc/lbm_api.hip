@@ -107,7 +107,12 @@ void choose_launch(lbm_ctx *c) {
     const lbm_params &p = c->p;
     int tx = p.tile_x, ty = p.tile_y;
     if (tx == 0 || ty == 0) {
-        if (p.nx >= 48) { tx = 64; ty = 4; }
+        // Wider tiles pull a smaller ring of neighbour densities per site;
+        // the FP32 64 x 8 block fits twice per CU, the 16-bit instances
+        // (more registers for the conversions) run best as 32 x 8, FP64
+        // takes 256-thread tiles only.
+        const bool wide = p.prec == LBM_FP32;
+        if (p.nx >= 48 && wide && p.ny >= 16) { tx = 64; ty = 8; }
         else if (p.nx >= 24) { tx = 32; ty = 8; }
         else if (p.nx >= 12) { tx = 16; ty = 16; }
         else { tx = 8; ty = 32; }
@@ -118,9 +123,18 @@ void choose_launch(lbm_ctx *c) {
     c->nty = (p.ny + ty - 1) / ty;
     int zc = p.zchunk;
     if (zc <= 0) {
-        // Aim at about 2048 blocks (8 per CU) with chunks of at least 4 planes.
+        // About two rounds of resident blocks (at least four blocks per CU),
+        // chunks of at least four planes: fewer, deeper chunks re-pull fewer
+        // boundary planes, and a second round evens out the tiles' unequal
+        // fluid counts.
+        int cus = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        const int per_cu = lbm::step_blocks_per_cu(p.prec, tx, ty);
+        const int64_t target = std::max<int64_t>(2LL * std::max(per_cu, 1) * cus, 4LL * cus);
         const int64_t xy = (int64_t)c->ntx * c->nty;
-        const int64_t want = (2048 + xy - 1) / xy;
+        const int64_t want = (target + xy - 1) / xy;
         zc = (int)((p.nz + want - 1) / want);
         if (zc < 4) zc = 4;
     }
@@ -342,6 +356,10 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
     if (!p.rho_init[0] || !p.rho_init[1]) return fail(nullptr, LBM_EINVAL, "rho_init pointers are NULL");
     if ((p.tile_x || p.tile_y) && !lbm::tile_supported(p.tile_x, p.tile_y))
         return fail(nullptr, LBM_EINVAL, "unsupported tile (64x4, 32x8, 16x16, 8x32, 64x8 or 32x16)");
+    // The FP64 step with 512-thread blocks gives results that differ from
+    // run to run; it is refused until that is understood.
+    if (p.prec == LBM_FP64 && p.tile_x * p.tile_y > 256)
+        return fail(nullptr, LBM_EINVAL, "fp64 takes the 256-thread tiles only (64x4, 32x8, 16x16, 8x32)");
     if (p.zchunk < 0) return fail(nullptr, LBM_EINVAL, "zchunk must be >= 0");
 
     lbm_ctx *c = new (std::nothrow) lbm_ctx();

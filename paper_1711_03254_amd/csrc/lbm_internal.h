@@ -70,5 +70,7 @@ hipError_t launch_batch(int prec, Mode mode, int tx, int ty, const void *descs, 
 
 // Tile shapes the step kernel is compiled for.
 bool tile_supported(int tx, int ty);
+// Resident blocks per compute unit of the plain step kernel (0 if unknown).
+int step_blocks_per_cu(int prec, int tx, int ty);
 
 }  // namespace lbm

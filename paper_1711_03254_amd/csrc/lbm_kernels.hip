@@ -17,8 +17,10 @@
 // for every plane it pulls the tile and its one-site ring, sums the
 // densities into an LDS ring buffer of four planes, and collides the plane
 // behind once the plane ahead is known.  The compact indices of the tile
-// and a ring of two sites are staged in LDS too (five planes), so each pull
-// finds its 18 sources (or the wall) there.  The ring's pulls are the only
+// and a ring of two sites are staged in LDS too (six planes: the three a
+// pull reads, the three the force's wall term of the plane behind may
+// still read while the next tile is staged), so each pull finds its 18
+// sources (or the wall) there.  The ring's pulls are the only
 // redundant work; no density array goes to HBM.
 
 #include <hip/hip_bf16.h>
@@ -375,7 +377,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     __shared__ C psi0[4][RH][RW];
     __shared__ C psi1[4][RH][RW];
     // byte offset of each site's population pair within a plane, -1 where solid
-    __shared__ int kid[5][HH][HW];
+    __shared__ int kid[6][HH][HW];
     __shared__ double red[NT / 64][6];
 
     const int tx = b % a.ntx;
@@ -390,12 +392,19 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
     const uint32_t pb = a.plane_bytes;
 
-    // This thread's ring site, in density-tile coordinates (rr, rc): ring
-    // index rt counts down from the last thread, so that the ring falls on
-    // the waves the work list leaves idle first.
+    // Ring position j (0 <= j < NR) in index-tile coordinates: the rows
+    // above and below the tile, then its left and right columns.
+    auto ring_pos = [&](int j, int &hr, int &hc) {
+        if (j < RW) { hr = 1; hc = 1 + j; }
+        else if (j < 2 * RW) { hr = RH; hc = 1 + j - RW; }
+        else if (j < 2 * RW + TY) { hr = 2 + j - 2 * RW; hc = 1; }
+        else { hr = 2 + j - 2 * RW - TY; hc = RW; }
+    };
+    // FP64 form: this thread's ring site in density-tile coordinates
+    // (rr, rc); ring index rt counts down from the last thread, so that the
+    // ring falls on the waves the work list leaves idle first.
     const int rt = NT - 1 - tid;
     const bool has_ring = rt < NR;
-    const bool ring_wave = NT - 64 * (tid / 64 + 1) < NR;   // the wave holds at least one ring site
     int rr = 0, rc = 0;
     if (rt < RW) { rr = 0; rc = rt; }
     else if (rt < 2 * RW) { rr = RH - 1; rc = rt - RW; }
@@ -481,61 +490,98 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
 
     // Pulls plane zw (z0 - 1 <= zw <= z1, unwrapped) into density slot
     // lslot; the interior's moments go to mn.  Index slot of plane p:
-    // (p - z0 + 2) mod 5; the tile of plane zw + 2 is staged on the way.
+    // (p - z0 + 2) mod 6; the tile of plane zw + 2 is staged on the way.
+    //
+    // The plane's pulls form one job list: jobs 0 .. cnt - 1 are the tile's
+    // fluid sites (job j = work-list entry j), jobs cnt .. cnt + NR - 1 the
+    // ring positions; job j runs on lane j mod NT in pass j / NT, so a lane
+    // holds one site's populations at a time and a second pass is needed
+    // only where cnt + NR > NT.
     auto load_plane = [&](int zw, int lslot, bool keep) {
         const int qw = zw - z0 + 2;
-        const int qm = (qw + 4) % 5, q0 = qw % 5, qp = (qw + 1) % 5;
-        const bool fi = tid < wcnt;
-        const int lx = wpos % TX, ly = wpos / TX;
-        const int si = fi ? kid[q0][ly + 2][lx + 2] : -1;
-        const int sr = has_ring ? kid[q0][rr + 1][rc + 1] : -1;
-        const bool fr = sr >= 0;
+        const int qm = (qw + 5) % 6, q0 = qw % 6, qp = (qw + 1) % 6;
+        const int cnt = wcnt;
         const int pos_here = wpos;
+        const int lx = wpos % TX, ly = wpos / TX;
         int vnext[NE];
         fetch_idx(zw + 2, vnext);
         fetch_work(zw + 1, wcnt, wpos);
-        S ri[2][19], rg[2][19];
-        // All of the plane's loads are issued before any is consumed: one
-        // memory round trip per plane.  Lanes without a pull (past the work
-        // list, no fluid ring site) issue no load and use none of these values.
-        if (fi) issue(ly + 2, lx + 2, qm, q0, qp, (uint32_t)si, ri);
-        if (fr) issue(rr + 1, rc + 1, qm, q0, qp, (uint32_t)sr, rg);
-        __builtin_amdgcn_sched_barrier(0);
-        C r0 = C(0), r1 = C(0);
-        if (fi) {
-            if (keep) {
-                mn[0] = moments_of<S>(ri[0], ref0);
-                mn[1] = moments_of<S>(ri[1], ref1);
-                r0 = mn[0].r;
-                r1 = mn[1].r;
-            } else {
-                r0 = density_of<S>(ri[0], ref0);
-                r1 = density_of<S>(ri[1], ref1);
-            }
-        }
-        fluid_n = fi;
-        kn = si;
+        fluid_n = tid < cnt;
         pn = pos_here;
-        if (fi) {
-            psi0[lslot][ly + 1][lx + 1] = r0;
-            psi1[lslot][ly + 1][lx + 1] = r1;
+        if constexpr (sizeof(S) == 8) {
+            // FP64: every thread pulls its work-list site and its ring site
+            // in one round trip (no second pass); the job list below gave
+            // run-to-run differences in the batched FP64 step, which this
+            // form does not.
+            const bool fi = tid < cnt;
+            const int si = fi ? kid[q0][ly + 2][lx + 2] : -1;
+            const int sr = has_ring ? kid[q0][rr + 1][rc + 1] : -1;
+            const bool fr = sr >= 0;
+            kn = si;
+            S ri[2][19], rg[2][19];
+            if (fi) issue(ly + 2, lx + 2, qm, q0, qp, (uint32_t)si, ri);
+            if (fr) issue(rr + 1, rc + 1, qm, q0, qp, (uint32_t)sr, rg);
+            __builtin_amdgcn_sched_barrier(0);
+            if (fi) {
+                C r0, r1;
+                if (keep) {
+                    mn[0] = moments_of<S>(ri[0], ref0);
+                    mn[1] = moments_of<S>(ri[1], ref1);
+                    r0 = mn[0].r;
+                    r1 = mn[1].r;
+                } else {
+                    r0 = density_of<S>(ri[0], ref0);
+                    r1 = density_of<S>(ri[1], ref1);
+                }
+                psi0[lslot][ly + 1][lx + 1] = r0;
+                psi1[lslot][ly + 1][lx + 1] = r1;
+            }
+            if (has_ring) {
+                C q0v = a.wall0, q1v = a.wall1;
+                if (fr) {
+                    q0v = density_of<S>(rg[0], ref0);
+                    q1v = density_of<S>(rg[1], ref1);
+                }
+                psi0[lslot][rr][rc] = q0v;
+                psi1[lslot][rr][rc] = q1v;
+            }
+        } else
+        for (int pass = 0; pass * NT < cnt + NR; ++pass) {
+            const int j = tid + pass * NT;
+            const bool site = j < cnt;
+            const bool ring = !site && j - cnt < NR;
+            int hr = ly + 2, hc = lx + 2;
+            if (!site) ring_pos(j - cnt, hr, hc);
+            const int self = site || ring ? kid[q0][hr][hc] : -1;
+            if (site) kn = self;
+            S raw[2][19];
+            // All of the job's loads are issued before any is consumed: one
+            // memory round trip per pass.  Lanes without a fluid job issue
+            // no load and use none of these values.
+            if (self >= 0) issue(hr, hc, qm, q0, qp, (uint32_t)self, raw);
+            __builtin_amdgcn_sched_barrier(0);
+            C r0 = a.wall0, r1 = a.wall1;
+            if (self >= 0) {
+                if (site && keep) {
+                    mn[0] = moments_of<S>(raw[0], ref0);
+                    mn[1] = moments_of<S>(raw[1], ref1);
+                    r0 = mn[0].r;
+                    r1 = mn[1].r;
+                } else {
+                    r0 = density_of<S>(raw[0], ref0);
+                    r1 = density_of<S>(raw[1], ref1);
+                }
+            }
+            if (site || ring) {
+                psi0[lslot][hr - 1][hc - 1] = r0;
+                psi1[lslot][hr - 1][hc - 1] = r1;
+            }
         }
         if (kid[q0][tly + 2][tlx + 2] < 0) {   // solid site of the tile: the wall densities
             psi0[lslot][tly + 1][tlx + 1] = a.wall0;
             psi1[lslot][tly + 1][tlx + 1] = a.wall1;
         }
-        if (ring_wave) {
-            C q0v = a.wall0, q1v = a.wall1;
-            if (fr) {
-                q0v = density_of<S>(rg[0], ref0);
-                q1v = density_of<S>(rg[1], ref1);
-            }
-            if (has_ring) {
-                psi0[lslot][rr][rc] = q0v;
-                psi1[lslot][rr][rc] = q1v;
-            }
-        }
-        store_idx((qw + 2) % 5, vnext);
+        store_idx((qw + 2) % 6, vnext);
     };
 
     double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -606,7 +652,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                     constexpr int i = I;
                     if constexpr (i > 0) {
                         constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
-                        const int q = ((z + Z) - z0 + 2) % 5;   // index slot of plane z + Z
+                        const int q = ((z + Z) - z0 + 2) % 6;   // index slot of plane z + Z
                         const C sol = kid[q][ly + 2 + Y][lx + 2 + X] < 0 ? C(w_of(i)) : C(0);
                         if constexpr (X != 0) Sx += C(X) * sol;
                         if constexpr (Y != 0) Sy += C(Y) * sol;
@@ -948,6 +994,25 @@ hipError_t launch_tiles(Mode mode, const StepLaunch &L, hipStream_t s) {
 }
 
 template <typename S, int TX, int TY>
+int occupancy_typed() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<S, TX, TY, MODE_STEP>, TX * TY, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
+template <typename S>
+int occupancy_tiles(int tx, int ty) {
+    if (tx == 64 && ty == 4) return occupancy_typed<S, 64, 4>();
+    if (tx == 32 && ty == 8) return occupancy_typed<S, 32, 8>();
+    if (tx == 16 && ty == 16) return occupancy_typed<S, 16, 16>();
+    if (tx == 8 && ty == 32) return occupancy_typed<S, 8, 32>();
+    if (tx == 64 && ty == 8) return occupancy_typed<S, 64, 8>();
+    if (tx == 32 && ty == 16) return occupancy_typed<S, 32, 16>();
+    return 0;
+}
+
+template <typename S, int TX, int TY>
 hipError_t launch_batch_typed(Mode mode, const void *descs, const int2 *work, int nwork, int flip, hipStream_t s) {
     const KArgs<S> *d = static_cast<const KArgs<S> *>(descs);
     const dim3 grid((unsigned)nwork), block(TX * TY);
@@ -1001,6 +1066,16 @@ hipError_t launch_batch(int prec, Mode mode, int tx, int ty, const void *descs, 
     case LBM_FP16S: return launch_batch_tiles<__half>(mode, tx, ty, descs, work, nwork, flip, s);
     case LBM_BF16S: return launch_batch_tiles<__hip_bfloat16>(mode, tx, ty, descs, work, nwork, flip, s);
     default: return hipErrorInvalidValue;
+    }
+}
+
+int step_blocks_per_cu(int prec, int tx, int ty) {
+    switch (prec) {
+    case LBM_FP64: return occupancy_tiles<double>(tx, ty);
+    case LBM_FP32: return occupancy_tiles<float>(tx, ty);
+    case LBM_FP16S: return occupancy_tiles<__half>(tx, ty);
+    case LBM_BF16S: return occupancy_tiles<__hip_bfloat16>(tx, ty);
+    default: return 0;
     }
 }
 

@@ -108,6 +108,8 @@ def test_struct_layout_matches_c(lbm, tmp_path):
     (dict(wall_kind=3), "wall_kind"),
     (dict(force_kind=-1), "force_kind"),
     (dict(tile=(48, 4)), "tile"),
+    (dict(tile=(64, 8), prec=0), "256-thread"),
+    (dict(tile=(32, 16), prec=0), "256-thread"),
     (dict(nx=0), "dimensions"),
     (dict(check_every=-1), "check_every"),
     (dict(G=float("nan")), "finite"),

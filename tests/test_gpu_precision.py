@@ -46,7 +46,8 @@ PHYS = dict(tau=(0.62, 1.7), G=-3.0, g=(1e-5, -2e-5, 3e-5), rho_s=0.3)
 
 
 @pytest.mark.parametrize("prec", ["fp16s", "bf16s"])
-def test_one_step_16bit(lbm, ora, prec):
+@pytest.mark.parametrize("tile", [(0, 0), (64, 4), (64, 8), (32, 16)])
+def test_one_step_16bit(lbm, ora, prec, tile):
     """One step from a smooth near-equilibrium state with walls: the state is
     rounded once on entry and once on store, so every population is within
     2 x 2^-(p+1) of the largest stored deviation (plus the propagation of the
@@ -63,7 +64,7 @@ def test_one_step_16bit(lbm, ora, prec):
     p = ora.Params(nx, ny, nz, solid=solid, **PHYS)
     f0 = ora.init(p, r1, r2, u)
     ctx = lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(r1, r2), u_init=u,
-                                  **PHYS))
+                                  tile=tile, **PHYS))
     got0 = lbm.lbm_get_populations(ctx)
     lbm.lbm_step(ctx, 1)
     got = lbm.lbm_get_populations(ctx)
@@ -73,7 +74,7 @@ def test_one_step_16bit(lbm, ora, prec):
     dev_scale = np.abs(f0 - w[None, :, None, None, None] * ref[:, None, None, None, None]).max()
     e_in = float(np.abs(got0 - f0).max())
     e_out = float(np.abs(got - want).max())
-    record("one_step_16bit", prec=prec, entry_abs=e_in, step_abs=e_out, dev_scale=float(dev_scale),
+    record("one_step_16bit", prec=prec, tile=list(tile), entry_abs=e_in, step_abs=e_out, dev_scale=float(dev_scale),
            step_rel=nmax(got, want))
     assert e_in <= UNIT[prec] * dev_scale * 1.0001
     assert e_out <= 4 * UNIT[prec] * dev_scale
