@@ -129,7 +129,7 @@ def ensemble(lbm, torch, steps, warmup):
         nz, ny, nx = d["shape"]
         ctxs.append(lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.LBM_FP32, solid=d["solid"],
                                             rho_init=(d["rho_A"], d["rho_B"]), tau=d["tau"], G=d["G"], g=d["g"],
-                                            rho_s=d["rho_s"], stream=stream, tile=(64, 4))))
+                                            rho_s=d["rho_s"], stream=stream, tile=(64, 8))))
     nf = sum(lbm.lbm_info(c)["n_fluid"] for c in ctxs)
     for c in ctxs:
         lbm.lbm_step(c, warmup)
@@ -181,13 +181,16 @@ def warm_start(lbm):
     return out
 
 
-def traffic_for(kern_ms_unused, n_fluid):
+def traffic_for(kernel, n_fluid):
     """HBM bytes per step launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+    summary, if it was taken on the current kernel source, the same kernel
+    instance and the same workload; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     t = json.load(open(TRAFFIC_FILE))
-    if t.get("kernel_source_sha256_16") != kernel_hash():
+    if t.get("kernel_source_sha256_16") != kernel_hash() or t.get("kernel") != kernel:
+        return None
+    if f"{n_fluid} fluid sites" not in t.get("workload", ""):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -241,7 +244,7 @@ def main():
         print(f"# {prec}: {json.dumps(res[prec])}", file=sys.stderr, flush=True)
     # The same kernel on an all-fluid lattice of the same size (a droplet of
     # A in B, no solids): its bandwidth fraction without the geometry's
-    # solid sites, which the dense layout still stores and sweeps.
+    # partly solid tiles, whose lanes and ring pulls it spends on fewer sites.
     allf = {}
     if args.all_fluid:
         import numpy as np
@@ -264,14 +267,15 @@ def main():
         print(f"# warm start: {json.dumps(ws_res)}", file=sys.stderr, flush=True)
     main_r = res["fp32"]
     n_fluid = main_r["n_fluid"]
+    kname = "step_kernel<float,{},{},MODE_STEP>".format(*main_r["tile"])
     roof = {
         "bound": "hbm",
         "achieved": round(main_r["algorithmic_GBs"], 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(main_r["algorithmic_GBs"] / HBM_PEAK_GBS, 4),
-        "traffic": traffic_for(main_r["kernel_ms"], n_fluid),
-        "kernel": "step_kernel<float,64,4,MODE_STEP>",
+        "traffic": traffic_for(kname, n_fluid),
+        "kernel": kname,
         "algorithmic_bytes_per_launch": n_fluid * main_r["bytes_per_lu"],
         "kernel_ms": round(main_r["kernel_ms"], 4),
     }

@@ -16,7 +16,7 @@ import os
 
 import numpy as np
 
-TILES = ((64, 4), (64, 8), (32, 8), (32, 16), (16, 16), (8, 32))
+TILES = ((64, 4), (64, 8), (64, 16), (32, 8), (32, 16), (16, 16), (8, 32))
 ZCHUNKS = (8, 16, 32, 64)
 
 
@@ -29,9 +29,14 @@ def _time_config(lbm, torch, prec, dom, tile, zchunk, steps, warmup, stream):
     nz, ny, nx = dom["shape"]
     if tile[0] > 2 * nx and tile != TILES[-1]:
         return None  # a tile much wider than the lattice only idles lanes
-    ctx = lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=dom["solid"],
-                                  rho_init=(dom["rho_A"], dom["rho_B"]), tau=dom["tau"], G=dom["G"],
-                                  g=dom["g"], rho_s=dom["rho_s"], stream=stream, tile=tile, zchunk=zchunk))
+    try:
+        ctx = lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=dom["solid"],
+                                      rho_init=(dom["rho_A"], dom["rho_B"]), tau=dom["tau"], G=dom["G"],
+                                      g=dom["g"], rho_s=dom["rho_s"], stream=stream, tile=tile, zchunk=zchunk))
+    except lbm.LBMError as e:
+        if e.code == lbm.LBM_EINVAL:
+            return None  # a tile this precision is not compiled for
+        raise
     lbm.lbm_step(ctx, warmup)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)

@@ -103,16 +103,18 @@ double default_mass_tol(int prec) {
     }
 }
 
-void choose_launch(lbm_ctx *c) {
+// Launch shape of the step.  fluid: the fraction of fluid sites.
+void choose_launch(lbm_ctx *c, double fluid) {
     const lbm_params &p = c->p;
     int tx = p.tile_x, ty = p.tile_y;
     if (tx == 0 || ty == 0) {
-        // Wider tiles pull a smaller ring of neighbour densities per site;
-        // the FP32 64 x 8 block fits twice per CU, the 16-bit instances
-        // (more registers for the conversions) run best as 32 x 8, FP64
-        // takes 256-thread tiles only.
-        const bool wide = p.prec == LBM_FP32;
-        if (p.nx >= 48 && wide && p.ny >= 16) { tx = 64; ty = 8; }
+        // Wider tiles pull a smaller ring of neighbour densities per site.
+        // At FP32 the 64 x 16 block (1024 threads, one per CU) is taken
+        // where a plane's expected jobs (fluid sites plus the 164 ring
+        // positions) fit in one pass, else 64 x 8; the 16-bit instances
+        // (more registers for the conversions) and FP64 run best as 32 x 8.
+        if (p.prec == LBM_FP32 && p.nx >= 48 && p.ny >= 32 && fluid * 1024.0 + 164.0 <= 1024.0) { tx = 64; ty = 16; }
+        else if (p.prec == LBM_FP32 && p.nx >= 48 && p.ny >= 16) { tx = 64; ty = 8; }
         else if (p.nx >= 24) { tx = 32; ty = 8; }
         else if (p.nx >= 12) { tx = 16; ty = 16; }
         else { tx = 8; ty = 32; }
@@ -123,19 +125,17 @@ void choose_launch(lbm_ctx *c) {
     c->nty = (p.ny + ty - 1) / ty;
     int zc = p.zchunk;
     if (zc <= 0) {
-        // About two rounds of resident blocks (at least four blocks per CU),
-        // chunks of at least four planes: fewer, deeper chunks re-pull fewer
-        // boundary planes, and a second round evens out the tiles' unequal
-        // fluid counts.
+        // One round of resident blocks: as many z-chunks as fit beside the
+        // tile columns at the kernel's occupancy, each as deep as that
+        // allows (fewer chunks re-pull fewer boundary planes).
         int cus = 0, dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
-        const int per_cu = lbm::step_blocks_per_cu(p.prec, tx, ty);
-        const int64_t target = std::max<int64_t>(2LL * std::max(per_cu, 1) * cus, 4LL * cus);
+        const int64_t resident = (int64_t)std::max(lbm::step_blocks_per_cu(p.prec, tx, ty), 1) * cus;
         const int64_t xy = (int64_t)c->ntx * c->nty;
-        const int64_t want = (target + xy - 1) / xy;
-        zc = (int)((p.nz + want - 1) / want);
+        const int64_t chunks = std::max<int64_t>(resident / xy, 1);
+        zc = (int)((p.nz + chunks - 1) / chunks);
         if (zc < 4) zc = 4;
     }
     if (zc > p.nz) zc = p.nz;
@@ -355,7 +355,9 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         return fail(nullptr, LBM_EINVAL, "mass_tol must be >= 0 and rho_ref finite");
     if (!p.rho_init[0] || !p.rho_init[1]) return fail(nullptr, LBM_EINVAL, "rho_init pointers are NULL");
     if ((p.tile_x || p.tile_y) && !lbm::tile_supported(p.tile_x, p.tile_y))
-        return fail(nullptr, LBM_EINVAL, "unsupported tile (64x4, 32x8, 16x16, 8x32, 64x8 or 32x16)");
+        return fail(nullptr, LBM_EINVAL, "unsupported tile (64x4, 32x8, 16x16, 8x32, 64x8, 32x16 or 64x16)");
+    if (p.tile_x * p.tile_y > 512 && p.prec != LBM_FP32)
+        return fail(nullptr, LBM_EINVAL, "the 64x16 tile is compiled for fp32 only");
     // The FP64 step with 512-thread blocks gives results that differ from
     // run to run; it is refused until that is understood.
     if (p.prec == LBM_FP64 && p.tile_x * p.tile_y > 256)
@@ -378,7 +380,6 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         delete c;
         return rc;
     }
-    choose_launch(c);
 
     auto bail = [&](int rc) {
         g_init_error = c->err;
@@ -400,6 +401,11 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         if (!p.inputs_on_device) std::memcpy(solid_h.data(), p.solid, (size_t)c->N);
         else if (hipMemcpy(solid_h.data(), p.solid, c->N, hipMemcpyDeviceToHost) != hipSuccess)
             return bail(fail(c, LBM_EDEVICE, "cannot read the solid mask"));
+    }
+    {
+        int64_t nsolid = 0;
+        for (uint8_t v : solid_h) nsolid += v != 0;
+        choose_launch(c, 1.0 - (double)nsolid / (double)c->N);
     }
     std::vector<int32_t> idx_h;
     const int64_t nfl = build_index(p.solid ? solid_h.data() : nullptr, p.nx, p.ny, p.nz, c->tile_x, c->tile_y, idx_h);

@@ -990,6 +990,8 @@ hipError_t launch_tiles(Mode mode, const StepLaunch &L, hipStream_t s) {
     if (L.tile_x == 8 && L.tile_y == 32) return launch_typed<S, 8, 32>(mode, L, s);
     if (L.tile_x == 64 && L.tile_y == 8) return launch_typed<S, 64, 8>(mode, L, s);
     if (L.tile_x == 32 && L.tile_y == 16) return launch_typed<S, 32, 16>(mode, L, s);
+    if constexpr (std::is_same_v<S, float>)
+        if (L.tile_x == 64 && L.tile_y == 16) return launch_typed<S, 64, 16>(mode, L, s);
     return hipErrorInvalidValue;
 }
 
@@ -1009,6 +1011,8 @@ int occupancy_tiles(int tx, int ty) {
     if (tx == 8 && ty == 32) return occupancy_typed<S, 8, 32>();
     if (tx == 64 && ty == 8) return occupancy_typed<S, 64, 8>();
     if (tx == 32 && ty == 16) return occupancy_typed<S, 32, 16>();
+    if constexpr (std::is_same_v<S, float>)
+        if (tx == 64 && ty == 16) return occupancy_typed<S, 64, 16>();
     return 0;
 }
 
@@ -1033,6 +1037,8 @@ hipError_t launch_batch_tiles(Mode mode, int tx, int ty, const void *descs, cons
     if (tx == 8 && ty == 32) return launch_batch_typed<S, 8, 32>(mode, descs, work, nwork, flip, s);
     if (tx == 64 && ty == 8) return launch_batch_typed<S, 64, 8>(mode, descs, work, nwork, flip, s);
     if (tx == 32 && ty == 16) return launch_batch_typed<S, 32, 16>(mode, descs, work, nwork, flip, s);
+    if constexpr (std::is_same_v<S, float>)
+        if (tx == 64 && ty == 16) return launch_batch_typed<S, 64, 16>(mode, descs, work, nwork, flip, s);
     return hipErrorInvalidValue;
 }
 
@@ -1081,7 +1087,7 @@ int step_blocks_per_cu(int prec, int tx, int ty) {
 
 bool tile_supported(int tx, int ty) {
     return (tx == 64 && ty == 4) || (tx == 32 && ty == 8) || (tx == 16 && ty == 16) || (tx == 8 && ty == 32) ||
-           (tx == 64 && ty == 8) || (tx == 32 && ty == 16);
+           (tx == 64 && ty == 8) || (tx == 32 && ty == 16) || (tx == 64 && ty == 16);
 }
 
 hipError_t launch_step(int prec, Mode mode, const StepLaunch &L, hipStream_t s) {
