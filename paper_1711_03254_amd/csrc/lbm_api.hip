@@ -52,6 +52,7 @@ struct lbm_batch {
     void *descs_dev = nullptr;
     int2 *work_dev = nullptr;
     int nwork = 0;
+    std::vector<int> zchunk, nzc;   // per domain: the batch's z-chunk and chunk count
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graphs_off = false;
@@ -690,14 +691,41 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, lbm_batch **out) {
     b->tile_y = ctxs[0]->tile_y;
     b->desc_size = lbm::batch_desc_size(b->prec);
     b->descs_host.resize(b->desc_size * n);
+    // Z-chunks of the batch.  A context's own z-chunk fills the GPU with
+    // that one domain; a batch that fills it several times over runs
+    // deeper chunks (at least 16 planes: fewer boundary planes re-pulled),
+    // never more blocks per domain than the context's own, so each keeps
+    // its partial-sum slots.
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctxs[0]->device) != hipSuccess || cus <= 0)
+            cus = 256;
+        const int64_t resident =
+            (int64_t)std::max(lbm::step_blocks_per_cu(b->prec, b->tile_x, b->tile_y), 1) * cus;
+        b->zchunk.resize(n);
+        b->nzc.resize(n);
+        int64_t deep = 0;
+        for (int d = 0; d < n; ++d) {
+            const lbm_ctx *c = ctxs[d];
+            b->zchunk[d] = std::max(c->zchunk, std::min(16, c->p.nz));
+            b->nzc[d] = (c->p.nz + b->zchunk[d] - 1) / b->zchunk[d];
+            deep += (int64_t)c->ntx * c->nty * b->nzc[d];
+        }
+        if (deep < resident)
+            for (int d = 0; d < n; ++d) {
+                b->zchunk[d] = ctxs[d]->zchunk;
+                b->nzc[d] = ctxs[d]->nzc;
+            }
+    }
+    auto bblocks = [&](int d) { return ctxs[d]->ntx * ctxs[d]->nty * b->nzc[d]; };
     // Work list: every tile of every domain, domain by domain, the largest
     // domains first so that their long columns of work start early.
     std::vector<int> order(n);
     for (int d = 0; d < n; ++d) order[d] = d;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nblocks(ctxs[x]) > nblocks(ctxs[y]); });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return bblocks(x) > bblocks(y); });
     std::vector<int2> work;
     for (int d : order)
-        for (int k = 0; k < nblocks(ctxs[d]); ++k) work.push_back(make_int2(d, k));
+        for (int k = 0; k < bblocks(d); ++k) work.push_back(make_int2(d, k));
     b->nwork = (int)work.size();
     auto bail = [&](int rc) {
         g_init_error = b->err;
@@ -725,6 +753,8 @@ int upload_descs(lbm_batch *b) {
     for (size_t d = 0; d < b->ctx.size(); ++d) {
         lbm_ctx *c = b->ctx[d];
         lbm::StepLaunch L = make_launch(c, c->f[c->cur], c->f[1 - c->cur]);
+        L.zchunk = b->zchunk[d];
+        L.nzc = b->nzc[d];
         lbm::fill_batch_desc(b->prec, L, b->descs_host.data() + d * b->desc_size);
     }
     if (hipMemcpyAsync(b->descs_dev, b->descs_host.data(), b->descs_host.size(), hipMemcpyHostToDevice, b->stream) !=
@@ -814,8 +844,11 @@ int lbm_batch_step(lbm_batch *b, int64_t n) {
             advance(1);
             flip ^= 1;
             ++k;
-            for (lbm_ctx *c : due) {
-                if (lbm::launch_finalize(c->partials, nblocks(c), c->red_dev, b->stream) != hipSuccess ||
+            for (size_t d = 0; d < b->ctx.size(); ++d) {
+                lbm_ctx *c = b->ctx[d];
+                if (std::find(due.begin(), due.end(), c) == due.end()) continue;
+                const int nb = c->ntx * c->nty * b->nzc[d];   // the batch's blocks of this domain
+                if (lbm::launch_finalize(c->partials, nb, c->red_dev, b->stream) != hipSuccess ||
                     hipMemcpyAsync(c->red_host, c->red_dev, sizeof(double) * lbm::kPartialStride,
                                    hipMemcpyDeviceToHost, b->stream) != hipSuccess)
                     return bfail(b, LBM_EDEVICE, "batch check failed");

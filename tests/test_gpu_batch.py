@@ -110,3 +110,24 @@ def test_batch_rejects_mixed_contexts(lbm):
         lbm.lbm_batch_create([a, c])
     with pytest.raises(lbm.LBMError):
         lbm.lbm_batch_create([a, a])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_deep_batch_chunks_equal_single_domains(lbm, prec):
+    """A batch that fills the GPU several times over steps its domains in
+    deeper z-chunks than each context alone (fewer, longer blocks); results
+    stay bit for bit those of the domains stepped alone, and the periodic
+    FP64 check (summed over the batch's own blocks) passes."""
+    cases = [((64, 48, 48), 100 + k, 1.0 + k % 7, -3.0, 0.1 * (k % 3)) for k in range(40)]
+    singles = [make(lbm, prec, c) for c in cases]
+    for c in singles:
+        lbm.lbm_step(c, 9)
+    batched = [make(lbm, prec, c, check_every=(4 if k % 3 == 0 else 0)) for k, c in enumerate(cases)]
+    assert sum(lbm.lbm_info(c)["blocks"] for c in batched) > 2048   # the contexts' own chunks
+    b = lbm.lbm_batch_create(batched)
+    lbm.lbm_batch_step(b, 9)
+    for s, d in zip(singles, batched):
+        assert np.array_equal(lbm.lbm_get_populations(s), lbm.lbm_get_populations(d))
+    red = lbm.lbm_reduce(batched[0])
+    m0 = lbm.lbm_info(batched[0])["mass0"]
+    assert abs(red[0] - m0[0]) / m0[0] <= (1e-12 if prec == "fp64" else 1e-5)
