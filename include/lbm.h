@@ -89,8 +89,8 @@ typedef struct {
     const double *u_init;        /* 3N (component-major) initial velocity, or NULL for rest */
     void *stream;                /* hipStream_t to run on; NULL = a stream the library creates */
     int32_t tile_x, tile_y;      /* x-y tile of the step kernel (0 = library default; 64x4, 32x8,
-                                    16x16, 8x32, 64x8 or 32x16; FP64 takes the first four only,
-                                    others give LBM_EINVAL) */
+                                    16x16, 8x32, 64x8, 32x16 or 64x16; FP64 takes the first four
+                                    only, others give LBM_EINVAL) */
     int32_t zchunk;              /* z planes per block (0 = library default) */
     int32_t wall_kind;           /* 0: the wall force of Eq. (11) as it stands (W1, default);
                                     1: each component gives up its density share of the mixture's

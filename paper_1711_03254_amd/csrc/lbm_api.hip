@@ -110,12 +110,13 @@ void choose_launch(lbm_ctx *c, double fluid) {
     int tx = p.tile_x, ty = p.tile_y;
     if (tx == 0 || ty == 0) {
         // Wider tiles pull a smaller ring of neighbour densities per site.
-        // At FP32 the 64 x 16 block (1024 threads, one per CU) is taken
-        // where a plane's expected jobs (fluid sites plus the 164 ring
-        // positions) fit in one pass, else 64 x 8; the 16-bit instances
-        // (more registers for the conversions) and FP64 run best as 32 x 8.
-        if (p.prec == LBM_FP32 && p.nx >= 48 && p.ny >= 32 && fluid * 1024.0 + 164.0 <= 1024.0) { tx = 64; ty = 16; }
-        else if (p.prec == LBM_FP32 && p.nx >= 48 && p.ny >= 16) { tx = 64; ty = 8; }
+        // At 32 and 16 bits the 64 x 16 block (1024 threads, one per CU) is
+        // taken where a plane's expected jobs (fluid sites plus the 164
+        // ring positions) fit in one pass, else 64 x 8; FP64 (one wave per
+        // SIMD) runs best as 32 x 8.
+        const bool narrow = p.prec != LBM_FP64;
+        if (narrow && p.nx >= 48 && p.ny >= 32 && fluid * 1024.0 + 164.0 <= 1024.0) { tx = 64; ty = 16; }
+        else if (narrow && p.nx >= 48 && p.ny >= 16) { tx = 64; ty = 8; }
         else if (p.nx >= 24) { tx = 32; ty = 8; }
         else if (p.nx >= 12) { tx = 16; ty = 16; }
         else { tx = 8; ty = 32; }
@@ -357,8 +358,7 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
     if (!p.rho_init[0] || !p.rho_init[1]) return fail(nullptr, LBM_EINVAL, "rho_init pointers are NULL");
     if ((p.tile_x || p.tile_y) && !lbm::tile_supported(p.tile_x, p.tile_y))
         return fail(nullptr, LBM_EINVAL, "unsupported tile (64x4, 32x8, 16x16, 8x32, 64x8, 32x16 or 64x16)");
-    if (p.tile_x * p.tile_y > 512 && p.prec != LBM_FP32)
-        return fail(nullptr, LBM_EINVAL, "the 64x16 tile is compiled for fp32 only");
+
     // The FP64 step with 512-thread blocks gives results that differ from
     // run to run; it is refused until that is understood.
     if (p.prec == LBM_FP64 && p.tile_x * p.tile_y > 256)

@@ -66,31 +66,46 @@ __device__ __forceinline__ void sfor(F &&f) {
 // ---------------------------------------------------------------------------
 // Storage codecs.  16-bit formats hold the deviation f_i - w_i rho_ref[a].
 // ---------------------------------------------------------------------------
+// C is the arithmetic type; R the type a pulled population is held in until
+// its moments are taken: FP16 values are widened as they arrive (fewer
+// registers live across the pull than with the packed halves and their
+// conversions), BF16 values when they are used (widening is a shift).
 template <typename S> struct Codec;
 template <> struct Codec<double> {
     using C = double;
+    using R = double;
     static constexpr bool shifted = false;
     __device__ static double ld(double v) { return v; }
     __device__ static double st(double v) { return v; }
 };
 template <> struct Codec<float> {
     using C = float;
+    using R = float;
     static constexpr bool shifted = false;
     __device__ static float ld(float v) { return v; }
     __device__ static float st(float v) { return v; }
 };
 template <> struct Codec<__half> {
     using C = float;
+    using R = float;
     static constexpr bool shifted = true;
     __device__ static float ld(__half v) { return __half2float(v); }
     __device__ static __half st(float v) { return __float2half_rn(v); }
 };
 template <> struct Codec<__hip_bfloat16> {
     using C = float;
+    using R = __hip_bfloat16;
     static constexpr bool shifted = true;
     __device__ static float ld(__hip_bfloat16 v) { return __bfloat162float(v); }
     __device__ static __hip_bfloat16 st(float v) { return __float2bfloat16(v); }
 };
+
+// A held population as the arithmetic type.
+template <typename S>
+__device__ __forceinline__ typename Codec<S>::C held(typename Codec<S>::R v) {
+    if constexpr (std::is_same_v<typename Codec<S>::R, typename Codec<S>::C>) return v;
+    else return Codec<S>::ld(v);
+}
 
 template <typename S>
 struct KArgs {
@@ -140,7 +155,8 @@ struct U64Pair {
     uint64_t a, b;
 };
 template <typename S>
-__device__ __forceinline__ void pair_load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, S &a, S &b) {
+__device__ __forceinline__ void pair_load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, typename Codec<S>::R &a,
+                                          typename Codec<S>::R &b) {
     if constexpr (std::is_same_v<S, float>) {
         const uint64_t x = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
         a = __builtin_bit_cast(float, (uint32_t)(x & 0xffffffffu));
@@ -151,8 +167,15 @@ __device__ __forceinline__ void pair_load(__amdgpu_buffer_rsrc_t r, uint32_t v, 
         b = __builtin_bit_cast(double, x.b);
     } else {
         const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0);
-        a = __builtin_bit_cast(S, (unsigned short)(x & 0xffffu));
-        b = __builtin_bit_cast(S, (unsigned short)(x >> 16));
+        const S lo = __builtin_bit_cast(S, (unsigned short)(x & 0xffffu));
+        const S hi = __builtin_bit_cast(S, (unsigned short)(x >> 16));
+        if constexpr (std::is_same_v<typename Codec<S>::R, S>) {
+            a = lo;
+            b = hi;
+        } else {
+            a = Codec<S>::ld(lo);
+            b = Codec<S>::ld(hi);
+        }
     }
 }
 
@@ -194,15 +217,16 @@ template <int SGN, typename C> __device__ __forceinline__ void acc_signed(C &acc
 // f_i - w_i rho_ref) the shift is added back to the moments: sum_i w_i = 1,
 // sum_i w_i c_i = 0 and sum_i w_i c_i c_i = T0 I.
 template <typename S>
-__device__ __forceinline__ Moments<typename Codec<S>::C> moments_of(const S (&raw)[19], typename Codec<S>::C ref) {
+__device__ __forceinline__ Moments<typename Codec<S>::C> moments_of(const typename Codec<S>::R (&raw)[19],
+                                                                   typename Codec<S>::C ref) {
     using C = typename Codec<S>::C;
     const C z = C(-0.0);
     Moments<C> m{z, z, z, z, z, z, z, z, z, z};
-    m.r = Codec<S>::ld(raw[0]);
+    m.r = held<S>(raw[0]);
     sfor<9>([&](auto K) {
         constexpr int i = 2 * K + 1;
         constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
-        const C p = Codec<S>::ld(raw[i]), q = Codec<S>::ld(raw[i + 1]);
+        const C p = held<S>(raw[i]), q = held<S>(raw[i + 1]);
         const C s = p + q, d = p - q;
         m.r += s;
         acc_signed<X>(m.jx, d);
@@ -229,12 +253,13 @@ __device__ __forceinline__ Moments<typename Codec<S>::C> moments_of(const S (&ra
 // density is the same bits whether a block pulls it as a tile site or as a
 // ring site of a neighbouring tile.
 template <typename S>
-__device__ __forceinline__ typename Codec<S>::C density_of(const S (&raw)[19], typename Codec<S>::C ref) {
+__device__ __forceinline__ typename Codec<S>::C density_of(const typename Codec<S>::R (&raw)[19],
+                                                           typename Codec<S>::C ref) {
     using C = typename Codec<S>::C;
-    C r = Codec<S>::ld(raw[0]);
+    C r = held<S>(raw[0]);
     sfor<9>([&](auto K) {
         constexpr int i = 2 * K + 1;
-        r += Codec<S>::ld(raw[i]) + Codec<S>::ld(raw[i + 1]);
+        r += held<S>(raw[i]) + held<S>(raw[i + 1]);
     });
     if constexpr (Codec<S>::shifted) r += ref;
     return r;
@@ -458,7 +483,8 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     // qp: f_i = f*_i(x - c_i), or f*_opp(i)(x) when x - c_i is solid.  Both
     // members of an opposite pair are addressed from the odd member's plane
     // (the scalar offset), so the bounce-back is a select of lane offsets.
-    auto issue = [&](int hr, int hc, int qm, int q0, int qp, uint32_t self, S (&raw)[2][19]) {
+    using R = typename Codec<S>::R;
+    auto issue = [&](int hr, int hc, int qm, int q0, int qp, uint32_t self, R (&raw)[2][19]) {
         const uint32_t self_p = self + pb;
         sfor<19>([&](auto I) {
             constexpr int i = I;
@@ -518,7 +544,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
             const int sr = has_ring ? kid[q0][rr + 1][rc + 1] : -1;
             const bool fr = sr >= 0;
             kn = si;
-            S ri[2][19], rg[2][19];
+            R ri[2][19], rg[2][19];
             if (fi) issue(ly + 2, lx + 2, qm, q0, qp, (uint32_t)si, ri);
             if (fr) issue(rr + 1, rc + 1, qm, q0, qp, (uint32_t)sr, rg);
             __builtin_amdgcn_sched_barrier(0);
@@ -554,7 +580,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
             if (!site) ring_pos(j - cnt, hr, hc);
             const int self = site || ring ? kid[q0][hr][hc] : -1;
             if (site) kn = self;
-            S raw[2][19];
+            R raw[2][19];
             // All of the job's loads are issued before any is consumed: one
             // memory round trip per pass.  Lanes without a fluid job issue
             // no load and use none of these values.
@@ -766,8 +792,13 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     }
 }
 
+// Waves per SIMD the register allocator must allow: four for the 16-bit
+// instances (a few spilled registers cost less than a quarter of the waves,
+// and 1024-thread blocks need four), the natural count otherwise.
+template <typename S> constexpr int kMinWaves = sizeof(S) == 2 ? 4 : 1;
+
 template <typename S, int TX, int TY, int MODE>
-__global__ void __launch_bounds__(TX *TY) step_kernel(KArgs<S> a) {
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(kMinWaves<S>))) step_kernel(KArgs<S> a) {
     step_body<S, TX, TY, MODE>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
 }
 
@@ -775,7 +806,7 @@ __global__ void __launch_bounds__(TX *TY) step_kernel(KArgs<S> a) {
 // by domain; descs[d] describes domain d with (src, dst) of an even step,
 // swapped when flip is set.
 template <typename S, int TX, int TY, int MODE>
-__global__ void __launch_bounds__(TX *TY) batch_kernel(const KArgs<S> *descs, const int2 *work, int flip) {
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(kMinWaves<S>))) batch_kernel(const KArgs<S> *descs, const int2 *work, int flip) {
     const int2 w = work[xcd_remap(blockIdx.x, gridDim.x)];
     KArgs<S> a = descs[w.x];
     if (flip) {
@@ -990,7 +1021,7 @@ hipError_t launch_tiles(Mode mode, const StepLaunch &L, hipStream_t s) {
     if (L.tile_x == 8 && L.tile_y == 32) return launch_typed<S, 8, 32>(mode, L, s);
     if (L.tile_x == 64 && L.tile_y == 8) return launch_typed<S, 64, 8>(mode, L, s);
     if (L.tile_x == 32 && L.tile_y == 16) return launch_typed<S, 32, 16>(mode, L, s);
-    if constexpr (std::is_same_v<S, float>)
+    if constexpr (sizeof(S) <= 4)
         if (L.tile_x == 64 && L.tile_y == 16) return launch_typed<S, 64, 16>(mode, L, s);
     return hipErrorInvalidValue;
 }
@@ -1011,7 +1042,7 @@ int occupancy_tiles(int tx, int ty) {
     if (tx == 8 && ty == 32) return occupancy_typed<S, 8, 32>();
     if (tx == 64 && ty == 8) return occupancy_typed<S, 64, 8>();
     if (tx == 32 && ty == 16) return occupancy_typed<S, 32, 16>();
-    if constexpr (std::is_same_v<S, float>)
+    if constexpr (sizeof(S) <= 4)
         if (tx == 64 && ty == 16) return occupancy_typed<S, 64, 16>();
     return 0;
 }
@@ -1037,7 +1068,7 @@ hipError_t launch_batch_tiles(Mode mode, int tx, int ty, const void *descs, cons
     if (tx == 8 && ty == 32) return launch_batch_typed<S, 8, 32>(mode, descs, work, nwork, flip, s);
     if (tx == 64 && ty == 8) return launch_batch_typed<S, 64, 8>(mode, descs, work, nwork, flip, s);
     if (tx == 32 && ty == 16) return launch_batch_typed<S, 32, 16>(mode, descs, work, nwork, flip, s);
-    if constexpr (std::is_same_v<S, float>)
+    if constexpr (sizeof(S) <= 4)
         if (tx == 64 && ty == 16) return launch_batch_typed<S, 64, 16>(mode, descs, work, nwork, flip, s);
     return hipErrorInvalidValue;
 }

@@ -110,7 +110,7 @@ def test_struct_layout_matches_c(lbm, tmp_path):
     (dict(tile=(48, 4)), "tile"),
     (dict(tile=(64, 8), prec=0), "256-thread"),
     (dict(tile=(32, 16), prec=0), "256-thread"),
-    (dict(tile=(64, 16), prec=2), "fp32 only"),
+    (dict(tile=(64, 16), prec=0), "256-thread"),
     (dict(nx=0), "dimensions"),
     (dict(check_every=-1), "check_every"),
     (dict(G=float("nan")), "finite"),

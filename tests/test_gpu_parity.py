@@ -70,8 +70,8 @@ def gpu_ctx(lbm, shape, prec, solid, **kw):
 PHYS = dict(tau=(0.62, 1.7), G=-3.0, g=(1e-5, -2e-5, 3e-5), rho_s=0.3)
 
 
-# Every tile the library compiles; FP64 is refused the 512-thread ones,
-# 64 x 16 is compiled for FP32 only.
+# Every tile the library compiles; FP64 is refused the tiles of more than
+# 256 threads.
 TILE_CASES = [(p, t) for p in ("fp64", "fp32")
               for t in ((64, 4), (32, 8), (16, 16), (8, 32), (64, 8), (32, 16), (64, 16))
               if not (p == "fp64" and t[0] * t[1] > 256)]

@@ -46,7 +46,7 @@ PHYS = dict(tau=(0.62, 1.7), G=-3.0, g=(1e-5, -2e-5, 3e-5), rho_s=0.3)
 
 
 @pytest.mark.parametrize("prec", ["fp16s", "bf16s"])
-@pytest.mark.parametrize("tile", [(0, 0), (64, 4), (64, 8), (32, 16)])
+@pytest.mark.parametrize("tile", [(0, 0), (64, 4), (32, 8), (64, 8), (32, 16), (64, 16)])
 def test_one_step_16bit(lbm, ora, prec, tile):
     """One step from a smooth near-equilibrium state with walls: the state is
     rounded once on entry and once on store, so every population is within
