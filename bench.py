@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS and % HBM peak (FP32 vs FP16-shifted); time-to-steady-state w/ warm start"
 KERNEL_SRC = os.path.join(ROOT, "paper_1711_03254_amd", "csrc", "lbm_kernels.hip")
+LAYOUT_SRC = os.path.join(ROOT, "paper_1711_03254_amd", "csrc", "lbm_api.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_fp32_packed_spheres_256.json")
 
 
@@ -48,7 +49,12 @@ def workload(n=256, G=-4.2, width=1.5):
 
 
 def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the step kernel and of the host code that lays out its data
+    (both decide the traffic the counters saw)."""
+    h = hashlib.sha256()
+    for path in (KERNEL_SRC, LAYOUT_SRC):
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def time_precision(lbm, torch, prec, solid, rA, rB, phys, steps, warmup, check_every):
@@ -188,7 +194,7 @@ def traffic_for(kernel, n_fluid):
     if not os.path.exists(TRAFFIC_FILE):
         return None
     t = json.load(open(TRAFFIC_FILE))
-    if t.get("kernel_source_sha256_16") != kernel_hash() or t.get("kernel") != kernel:
+    if t.get("kernel_and_layout_source_sha256_16") != kernel_hash() or t.get("kernel") != kernel:
         return None
     if f"{n_fluid} fluid sites" not in t.get("workload", ""):
         return None

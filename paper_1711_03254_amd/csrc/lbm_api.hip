@@ -271,22 +271,38 @@ int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u,
     return LBM_OK;
 }
 
+// Order of the positions (ly tx + lx) of a tile plane in storage: its left
+// and right columns first, each top to bottom, then the rows without them,
+// so that the sites a neighbouring tile pulls across a vertical edge are
+// contiguous (row by row they would be one per row).
+void tile_order(int tx, int ty, std::vector<int> &order) {
+    order.clear();
+    for (int ly = 0; ly < ty; ++ly) order.push_back(ly * tx);
+    if (tx > 1)
+        for (int ly = 0; ly < ty; ++ly) order.push_back(ly * tx + tx - 1);
+    for (int ly = 0; ly < ty; ++ly)
+        for (int lx = 1; lx < tx - 1; ++lx) order.push_back(ly * tx + lx);
+}
+
 // Compact index of the fluid sites: tile column by tile column (the step's
-// x-y tiles), z plane by plane, row by row within a tile, so that the sites
+// x-y tiles), z plane by plane, in tile_order within a tile, so that the sites
 // one block updates are contiguous in every population plane.
 int64_t build_index(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty, std::vector<int32_t> &idx) {
     const int64_t N = (int64_t)nx * ny * nz;
     idx.assign((size_t)N, -1);
     int64_t k = 0;
     const int ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty;
+    std::vector<int> order;
+    tile_order(tx, ty, order);
     for (int by = 0; by < nty; ++by)
         for (int bx = 0; bx < ntx; ++bx)
             for (int z = 0; z < nz; ++z)
-                for (int y = by * ty; y < std::min(ny, (by + 1) * ty); ++y)
-                    for (int x = bx * tx; x < std::min(nx, (bx + 1) * tx); ++x) {
-                        const int64_t s = x + (int64_t)nx * (y + (int64_t)ny * z);
-                        if (!solid || !solid[s]) idx[(size_t)s] = (int32_t)k++;
-                    }
+                for (int q : order) {
+                    const int x = bx * tx + q % tx, y = by * ty + q / tx;
+                    if (x >= nx || y >= ny) continue;
+                    const int64_t s = x + (int64_t)nx * (y + (int64_t)ny * z);
+                    if (!solid || !solid[s]) idx[(size_t)s] = (int32_t)k++;
+                }
     return k;
 }
 
@@ -297,6 +313,8 @@ int64_t build_index(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty
 void build_work(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty, std::vector<int32_t> &wstart,
                 std::vector<uint16_t> &wpos) {
     const int ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty;
+    std::vector<int> order;
+    tile_order(tx, ty, order);
     wstart.assign((size_t)ntx * nty * (nz + 1), 0);
     wpos.clear();
     for (int by = 0; by < nty; ++by)
@@ -304,12 +322,12 @@ void build_work(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty, st
             const size_t col = (size_t)(by * ntx + bx) * (nz + 1);
             for (int z = 0; z < nz; ++z) {
                 wstart[col + z] = (int32_t)wpos.size();
-                for (int ly = 0; ly < ty; ++ly)
-                    for (int lx = 0; lx < tx; ++lx) {
-                        const int x = (bx * tx + lx) % nx, y = (by * ty + ly) % ny;
-                        const int64_t s = x + (int64_t)nx * (y + (int64_t)ny * z);
-                        if (!solid || !solid[s]) wpos.push_back((uint16_t)(ly * tx + lx));
-                    }
+                for (int q : order) {
+                    const int lx = q % tx, ly = q / tx;
+                    const int x = (bx * tx + lx) % nx, y = (by * ty + ly) % ny;
+                    const int64_t s = x + (int64_t)nx * (y + (int64_t)ny * z);
+                    if (!solid || !solid[s]) wpos.push_back((uint16_t)q);
+                }
             }
             wstart[col + nz] = (int32_t)wpos.size();
         }
