@@ -222,8 +222,8 @@ def main():
                     help="also run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the step is measured on a single "
-              "MI355X; multi-GPU execution is not part of this build.", file=sys.stderr)
+        print(f"bench.py measures the step on one MI355X; runs on several GPUs are not supported "
+              f"(asked for {args.gpus}).", file=sys.stderr)
         sys.exit(2)
 
     import torch
