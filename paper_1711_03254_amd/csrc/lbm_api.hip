@@ -286,8 +286,11 @@ void tile_order(int tx, int ty, std::vector<int> &order) {
 
 // Compact index of the fluid sites: tile column by tile column (the step's
 // x-y tiles), z plane by plane, in tile_order within a tile, so that the sites
-// one block updates are contiguous in every population plane.
-int64_t build_index(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty, std::vector<int32_t> &idx) {
+// one block updates are contiguous in every population plane.  Each tile
+// plane's run starts on a multiple of align slots (128 bytes of pairs): no
+// line is written by two blocks.  Returns the slots used (fluid sites plus
+// the unused slots between runs).
+int64_t build_index(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty, int align, std::vector<int32_t> &idx) {
     const int64_t N = (int64_t)nx * ny * nz;
     idx.assign((size_t)N, -1);
     int64_t k = 0;
@@ -296,13 +299,15 @@ int64_t build_index(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty
     tile_order(tx, ty, order);
     for (int by = 0; by < nty; ++by)
         for (int bx = 0; bx < ntx; ++bx)
-            for (int z = 0; z < nz; ++z)
+            for (int z = 0; z < nz; ++z) {
                 for (int q : order) {
                     const int x = bx * tx + q % tx, y = by * ty + q / tx;
                     if (x >= nx || y >= ny) continue;
                     const int64_t s = x + (int64_t)nx * (y + (int64_t)ny * z);
                     if (!solid || !solid[s]) idx[(size_t)s] = (int32_t)k++;
                 }
+                k = (k + align - 1) / align * align;   // the next segment starts a 128-byte line
+            }
     return k;
 }
 
@@ -427,7 +432,9 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         choose_launch(c, 1.0 - (double)nsolid / (double)c->N);
     }
     std::vector<int32_t> idx_h;
-    const int64_t nfl = build_index(p.solid ? solid_h.data() : nullptr, p.nx, p.ny, p.nz, c->tile_x, c->tile_y, idx_h);
+    const int align = std::max(1, 128 / (2 * (int)esz));
+    const int64_t nfl =
+        build_index(p.solid ? solid_h.data() : nullptr, p.nx, p.ny, p.nz, c->tile_x, c->tile_y, align, idx_h);
     if (nfl == 0) return bail(fail(c, LBM_EINVAL, "the lattice has no fluid site"));
     // Each plane starts 256-byte aligned; the odd padding keeps the 38 planes
     // of a buffer from starting at the same offsets modulo large powers of two.
