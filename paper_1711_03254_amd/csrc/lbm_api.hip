@@ -112,8 +112,8 @@ void choose_launch(lbm_ctx *c, double fluid) {
         // Wider tiles pull a smaller ring of neighbour densities per site.
         // At 32 and 16 bits the 64 x 16 block (1024 threads, one per CU) is
         // taken where a plane's expected jobs (fluid sites plus the 164
-        // ring positions) fit in one pass, else 64 x 8; FP64 (one wave per
-        // SIMD) runs best as 32 x 8.
+        // ring positions) fit in one pass, else 64 x 8; FP64 (two waves per
+        // SIMD, 256-thread tiles only) runs as 32 x 8.
         const bool narrow = p.prec != LBM_FP64;
         if (narrow && p.nx >= 48 && p.ny >= 32 && fluid * 1024.0 + 164.0 <= 1024.0) { tx = 64; ty = 16; }
         else if (narrow && p.nx >= 48 && p.ny >= 16) { tx = 64; ty = 8; }

@@ -399,8 +399,10 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     static_assert(NR <= NT, "the ring must fit in the block");
     constexpr uint32_t ESZ = sizeof(S);
 
-    __shared__ C psi0[4][RH][RW];
-    __shared__ C psi1[4][RH][RW];
+    // Densities of both components per site, side by side: one LDS access
+    // moves a neighbour's pair.
+    struct alignas(2 * sizeof(C)) PsiPair { C a, b; };
+    __shared__ PsiPair psi[4][RH][RW];
     // byte offset of each site's population pair within a plane, -1 where solid
     __shared__ int kid[6][HH][HW];
     __shared__ double red[NT / 64][6];
@@ -559,8 +561,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                     r0 = density_of<S>(ri[0], ref0);
                     r1 = density_of<S>(ri[1], ref1);
                 }
-                psi0[lslot][ly + 1][lx + 1] = r0;
-                psi1[lslot][ly + 1][lx + 1] = r1;
+                psi[lslot][ly + 1][lx + 1] = PsiPair{r0, r1};
             }
             if (has_ring) {
                 C q0v = a.wall0, q1v = a.wall1;
@@ -568,8 +569,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                     q0v = density_of<S>(rg[0], ref0);
                     q1v = density_of<S>(rg[1], ref1);
                 }
-                psi0[lslot][rr][rc] = q0v;
-                psi1[lslot][rr][rc] = q1v;
+                psi[lslot][rr][rc] = PsiPair{q0v, q1v};
             }
         } else
         for (int pass = 0; pass * NT < cnt + NR; ++pass) {
@@ -599,13 +599,11 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                 }
             }
             if (site || ring) {
-                psi0[lslot][hr - 1][hc - 1] = r0;
-                psi1[lslot][hr - 1][hc - 1] = r1;
+                psi[lslot][hr - 1][hc - 1] = PsiPair{r0, r1};
             }
         }
         if (kid[q0][tly + 2][tlx + 2] < 0) {   // solid site of the tile: the wall densities
-            psi0[lslot][tly + 1][tlx + 1] = a.wall0;
-            psi1[lslot][tly + 1][tlx + 1] = a.wall1;
+            psi[lslot][tly + 1][tlx + 1] = PsiPair{a.wall0, a.wall1};
         }
         store_idx((qw + 2) % 6, vnext);
     };
@@ -653,8 +651,8 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                     constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
                     constexpr C wx = C(X * w_of(i)), wy = C(Y * w_of(i)), wz = C(Z * w_of(i));
                     const int sl = Z == 0 ? s0 : (Z > 0 ? sp : sm);
-                    const C p0 = psi0[sl][ly + 1 + Y][lx + 1 + X];
-                    const C p1 = psi1[sl][ly + 1 + Y][lx + 1 + X];
+                    const PsiPair pp = psi[sl][ly + 1 + Y][lx + 1 + X];
+                    const C p0 = pp.a, p1 = pp.b;
                     if constexpr (X != 0) { n0x += wx * p0; n1x += wx * p1; }
                     if constexpr (Y != 0) { n0y += wy * p0; n1y += wy * p1; }
                     if constexpr (Z != 0) { n0z += wz * p0; n1z += wz * p1; }
