@@ -95,3 +95,19 @@ def measure(rho_s, G=-4.2, tau=(1.0, 1.0), steps=20000, prec="fp64", wall_kind=0
 def calibrate(values=(-0.4, -0.2, 0.0, 0.2, 0.4), **kw):
     """theta(rho^s) over the given wall parameters."""
     return [measure(v, **kw) for v in values]
+
+
+def rho_s_for(theta_deg, table):
+    """The inverse of the calibration (Section 3.3 inverts theta = L(nu_1,
+    nu_2, rho^s) for the wall potential): rho^s for a target angle (inside
+    component A), linear between the two table rows that bracket it.  The
+    table (rows of calibrate at one pair of viscosities) must be increasing
+    in theta over the rows used; rows without a fitted angle are skipped.
+    Raises ValueError outside the table's range."""
+    rows = sorted((r["rho_s"], r["theta_deg"]) for r in table if np.isfinite(r["theta_deg"]))
+    for (r0, t0), (r1, t1) in zip(rows, rows[1:]):
+        if t1 <= t0:
+            raise ValueError("the calibration is not increasing in rho^s")
+        if t0 <= theta_deg <= t1:
+            return r0 + (theta_deg - t0) * (r1 - r0) / (t1 - t0)
+    raise ValueError(f"theta = {theta_deg} lies outside the calibrated range")

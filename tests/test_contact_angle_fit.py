@@ -1,6 +1,7 @@
 """Host-side pieces of the contact-angle calibration: interface location,
 circle fit and the angle at the wall plane, on synthetic fields."""
 import numpy as np
+import pytest
 
 from paper_1711_03254_amd import contact_angle as ca
 
@@ -29,3 +30,15 @@ def test_angle_at_the_wall_plane():
     assert abs(ca.angle_from_circle(0.5 - 5.0, 10.0) - 60.0) < 1e-9
     # a circle centred far above the wall touches it only at 180 degrees
     assert ca.angle_from_circle(100.0, 10.0) == 180.0
+
+
+def test_inverse_interpolates_between_bracketing_rows():
+    table = [{"rho_s": -0.3, "theta_deg": 55.0}, {"rho_s": -0.2, "theta_deg": 65.0},
+             {"rho_s": 0.0, "theta_deg": float("nan")}, {"rho_s": 0.2, "theta_deg": 115.0}]
+    assert abs(ca.rho_s_for(60.0, table) - (-0.25)) < 1e-12
+    assert abs(ca.rho_s_for(65.0, table) - (-0.2)) < 1e-12
+    assert abs(ca.rho_s_for(90.0, table) - 0.0) < 1e-12       # across the gap left by the unfitted row
+    with pytest.raises(ValueError):
+        ca.rho_s_for(150.0, table)
+    with pytest.raises(ValueError):
+        ca.rho_s_for(60.0, [{"rho_s": 0.1, "theta_deg": 70.0}, {"rho_s": 0.2, "theta_deg": 50.0}])

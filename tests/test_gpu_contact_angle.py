@@ -34,3 +34,27 @@ def test_contact_angle_symmetries():
     assert abs(th[0.2] + th[-0.2] - 180.0) <= 3.0
     assert th[-0.3] < th[-0.2] < th[0.2] < th[0.3]
     assert th[0.2] > 95.0
+
+
+@pytest.mark.parametrize("tau", [(1.0, 1.0), (0.6, 1.5)])
+def test_inverted_calibration_reproduces_the_angle(tau):
+    """Section 3.3's use of the calibration: for a target angle, the wall
+    potential interpolated from theta = L(nu_1, nu_2, rho^s) at these
+    viscosities gives that angle back when the droplet is run with it
+    (within 3 degrees: the interpolation is linear over steps of 0.1 in
+    rho^s, about 10 degrees)."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1711_03254_amd import contact_angle as ca, lbm
+    lbm.load_library()
+    table = ca.calibrate(values=(-0.5, -0.4, -0.3, -0.2, 0.2, 0.3, 0.4, 0.5), tau=tau, steps=20000)
+    rows = []
+    for target in (50.0, 130.0):
+        rs = ca.rho_s_for(target, table)
+        got = ca.measure(rs, tau=tau, steps=20000)["theta_deg"]
+        rows.append({"target": target, "rho_s": rs, "theta": got})
+        assert abs(got - target) <= 3.0, (tau, target, rs, got)
+    path = os.environ.get("PARITY_LOG")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps({"test": "contact_angle_inverse", "tau": tau, "rows": rows}) + "\n")
