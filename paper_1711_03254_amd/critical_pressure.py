@@ -107,7 +107,7 @@ def slug_position(rb, solid, minor=0.03):
 
 
 def ramp(sigma, theta_deg, D=10, H=40, L=160, Z=52, rho_s=0.4, G=-4.2, tau=(1.0, 1.0), steps=80000,
-         stages=STAGES, prec="fp32", slug=(78, 109), x0=54):
+         stages=STAGES, prec="fp32", slug=(78, 109), x0=54, wall_kind=0):
     """Runs the staged drive of Section 3.4 and reports, per stage, where
     the slug's centre is (unwrapped along x) and how far it moved.  The slug
     (400 sites of the second component, 40 sites long inside the narrow
@@ -127,7 +127,7 @@ def ramp(sigma, theta_deg, D=10, H=40, L=160, Z=52, rho_s=0.4, G=-4.2, tau=(1.0,
     for k, dev in enumerate(stages):
         g = gc * (1.0 + dev)
         ctx = lbm.lbm_init(lbm.Params(L, H + 2, 1, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(ra, rb),
-                                      tau=tau, G=G, g=(g, 0.0, 0.0), rho_s=rho_s))
+                                      tau=tau, G=G, g=(g, 0.0, 0.0), rho_s=rho_s, wall_kind=wall_kind))
         if f is not None:
             lbm.lbm_set_populations(ctx, f)
         lbm.lbm_step(ctx, steps)
@@ -139,7 +139,7 @@ def ramp(sigma, theta_deg, D=10, H=40, L=160, Z=52, rho_s=0.4, G=-4.2, tau=(1.0,
         travelled += move
         rows.append({"stage": dev, "g": g, "slug_x": start + travelled, "moved": move})
         pos = new
-    return {"sigma": sigma, "theta_deg": theta_deg, "D": D, "H": H, "L": L, "Z": Z, "rho_s": rho_s,
+    return {"sigma": sigma, "theta_deg": theta_deg, "D": D, "H": H, "L": L, "Z": Z, "rho_s": rho_s, "wall_kind": wall_kind,
             "exit_x": x0 + Z, "p_crit": pc, "g_crit": gc, "stages": rows}
 
 
