@@ -103,10 +103,11 @@ typedef struct {
  * populations to the equilibrium f = f_eq(rho_init, u_init) (Eq. 3; the
  * paper does not state the initial populations).  Records the initial
  * component masses for the periodic check.  On failure *out is NULL.
- * Size limits (LBM_EINVAL): fewer than 2^30 sites, and 11 direction planes
- * of the fluid sites' populations below 4 GiB (about 24 M fluid sites at
- * FP64, 48 M at FP32, 97 M with 16-bit storage).  Device memory: two
- * population buffers of 2 x 19 x n_fluid x storage bytes, plus 8 bytes
+ * Size limits (LBM_EINVAL): fewer than 2^30 sites, and 11 of the 19
+ * directions of the fluid sites' populations below 4 GiB (about 24 M fluid
+ * sites at FP64, 48 M at FP32, 97 M with 16-bit storage).  Device memory:
+ * two population buffers of about 2 x 22 x n_fluid x storage bytes (the 19
+ * directions are stored in two halves of 11 direction slots), plus 8 bytes
  * per site for the link mask and the site index. */
 int lbm_init(const lbm_params *p, lbm_ctx **out);
 

@@ -14,6 +14,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-result",
+    # The small-tile 16-bit instances are limited to three blocks per CU by
+    # their LDS, below the four waves per SIMD the register budget aims at.
+    "-Wno-pass-failed",
     # Fuse a * b + c only within one source expression: the fusion choices
     # are then the same in every instantiation of the step (each mode, tile
     # and the batched form), so they all produce the same bits.

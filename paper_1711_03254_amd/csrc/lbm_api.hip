@@ -16,7 +16,7 @@
 
 struct lbm_ctx {
     lbm_params p;               // copy; borrowed pointers cleared
-    int64_t N = 0, plane = 0, nfluid = 0;
+    int64_t N = 0, ngroups = 0, nfluid = 0;
     size_t esz = 0;
     void *f[2] = {nullptr, nullptr};
     int cur = 0;
@@ -154,7 +154,7 @@ lbm::StepLaunch make_launch(const lbm_ctx *c, const void *src, void *dst) {
     L.wstart = c->wstart;
     L.wpos = c->wpos;
     L.nx = p.nx; L.ny = p.ny; L.nz = p.nz;
-    L.plane = c->plane;
+    L.ngroups = c->ngroups;
     L.tile_x = c->tile_x; L.tile_y = c->tile_y; L.zchunk = c->zchunk;
     L.ntx = c->ntx; L.nty = c->nty; L.nzc = c->nzc;
     L.tau0 = p.tau[0]; L.tau1 = p.tau[1]; L.G = p.G;
@@ -262,7 +262,7 @@ int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u,
     HIPCHK(c, hipMemcpyAsync(c->stage + c->N, vr1, NB, hipMemcpyHostToDevice, c->stream));
     if (vu) HIPCHK(c, hipMemcpyAsync(c->stage + 2 * c->N, vu, 3 * NB, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, lbm::launch_init_fields(c->p.prec, c->f[c->cur], c->links, c->idx, c->stage, c->stage + c->N,
-                                      vu ? c->stage + 2 * c->N : nullptr, c->p.nx, c->p.ny, c->p.nz, c->plane,
+                                      vu ? c->stage + 2 * c->N : nullptr, c->p.nx, c->p.ny, c->p.nz, c->ngroups,
                                       c->p.eq_kind, c->ref, c->stream));
     rc = measure(c, nullptr, nullptr, nullptr);
     if (rc) return rc;
@@ -271,25 +271,30 @@ int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u,
     return LBM_OK;
 }
 
-// Order of the positions (ly tx + lx) of a tile plane in storage: its left
-// and right columns first, each top to bottom, then the rows without them,
-// so that the sites a neighbouring tile pulls across a vertical edge are
-// contiguous (row by row they would be one per row).
+// Order of the positions (ly tx + lx) of a tile plane in storage: its two
+// leftmost and two rightmost columns first, each top to bottom, then the
+// rows without them.  A neighbouring tile's ring pulls read the column next
+// to the edge (for the directions pointing into this tile) as well as the
+// edge column itself, so both are contiguous (row by row they would be one
+// site per row).
 void tile_order(int tx, int ty, std::vector<int> &order) {
     order.clear();
-    for (int ly = 0; ly < ty; ++ly) order.push_back(ly * tx);
-    if (tx > 1)
-        for (int ly = 0; ly < ty; ++ly) order.push_back(ly * tx + tx - 1);
+    std::vector<int> cols;
+    for (int c : {0, 1, tx - 2, tx - 1})
+        if (c >= 0 && c < tx && std::find(cols.begin(), cols.end(), c) == cols.end()) cols.push_back(c);
+    for (int c : cols)
+        for (int ly = 0; ly < ty; ++ly) order.push_back(ly * tx + c);
     for (int ly = 0; ly < ty; ++ly)
-        for (int lx = 1; lx < tx - 1; ++lx) order.push_back(ly * tx + lx);
+        for (int lx = 0; lx < tx; ++lx)
+            if (std::find(cols.begin(), cols.end(), lx) == cols.end()) order.push_back(ly * tx + lx);
 }
 
-// Compact index of the fluid sites: tile column by tile column (the step's
-// x-y tiles), z plane by plane, in tile_order within a tile, so that the sites
-// one block updates are contiguous in every population plane.  Each tile
-// plane's run starts on a multiple of align slots (128 bytes of pairs): no
-// line is written by two blocks.  Returns the slots used (fluid sites plus
-// the unused slots between runs).
+// Slots of the fluid sites: z plane by plane, and within a plane tile by
+// tile (the step's x-y tiles) in tile_order, so that the sites one block
+// updates in a plane are contiguous.  Each tile plane's run starts on a
+// multiple of align slots (a slot group): no group, hence no memory line, is
+// written by two blocks.  Returns the slots used (fluid sites plus the
+// unused slots between runs).
 int64_t build_index(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty, int align, std::vector<int32_t> &idx) {
     const int64_t N = (int64_t)nx * ny * nz;
     idx.assign((size_t)N, -1);
@@ -297,17 +302,20 @@ int64_t build_index(const uint8_t *solid, int nx, int ny, int nz, int tx, int ty
     const int ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty;
     std::vector<int> order;
     tile_order(tx, ty, order);
-    for (int by = 0; by < nty; ++by)
-        for (int bx = 0; bx < ntx; ++bx)
-            for (int z = 0; z < nz; ++z) {
-                for (int q : order) {
-                    const int x = bx * tx + q % tx, y = by * ty + q / tx;
-                    if (x >= nx || y >= ny) continue;
-                    const int64_t s = x + (int64_t)nx * (y + (int64_t)ny * z);
-                    if (!solid || !solid[s]) idx[(size_t)s] = (int32_t)k++;
-                }
-                k = (k + align - 1) / align * align;   // the next segment starts a 128-byte line
-            }
+    auto segment = [&](int bx, int by, int z) {
+        for (int q : order) {
+            const int x = bx * tx + q % tx, y = by * ty + q / tx;
+            if (x >= nx || y >= ny) continue;
+            const int64_t s = x + (int64_t)nx * (y + (int64_t)ny * z);
+            if (!solid || !solid[s]) idx[(size_t)s] = (int32_t)k++;
+        }
+        k = (k + align - 1) / align * align;   // the next segment starts a slot group
+    };
+    // Plane by plane: the blocks of one z-chunk march through neighbouring
+    // memory at any one time (2-4 % faster than column by column).
+    for (int z = 0; z < nz; ++z)
+        for (int by = 0; by < nty; ++by)
+            for (int bx = 0; bx < ntx; ++bx) segment(bx, by, z);
     return k;
 }
 
@@ -432,18 +440,18 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         choose_launch(c, 1.0 - (double)nsolid / (double)c->N);
     }
     std::vector<int32_t> idx_h;
-    const int align = std::max(1, 128 / (2 * (int)esz));
-    const int64_t nfl =
-        build_index(p.solid ? solid_h.data() : nullptr, p.nx, p.ny, p.nz, c->tile_x, c->tile_y, align, idx_h);
+    const int64_t nfl = build_index(p.solid ? solid_h.data() : nullptr, p.nx, p.ny, p.nz, c->tile_x, c->tile_y,
+                                    lbm::kGroup, idx_h);
     if (nfl == 0) return bail(fail(c, LBM_EINVAL, "the lattice has no fluid site"));
-    // Each plane starts 256-byte aligned; the odd padding keeps the 38 planes
-    // of a buffer from starting at the same offsets modulo large powers of two.
-    c->plane = (nfl + 127) / 128 * 128 + 128 * 13;
-    // The step addresses 11 planes of component pairs with 32-bit byte offsets.
-    if (11 * 2 * (uint64_t)c->plane * esz >= (1ull << 32))
-        return bail(fail(c, LBM_EINVAL, "lattice too large: 11 population planes must stay below 4 GiB"));
+    // Groups of slots per buffer half, with 13 spare groups so that the two
+    // halves do not start at offsets equal modulo large powers of two.
+    c->ngroups = (nfl + lbm::kGroup - 1) / lbm::kGroup + 13;
+    const uint64_t half_bytes = (uint64_t)c->ngroups * lbm::kHalfDirs * lbm::kGroup * 2 * esz;
+    // The step addresses a buffer half with 32-bit byte offsets.
+    if (half_bytes >= (1ull << 32))
+        return bail(fail(c, LBM_EINVAL, "lattice too large: a half of the population storage must stay below 4 GiB"));
 
-    const size_t fbytes = (size_t)2 * 19 * c->plane * esz;
+    const size_t fbytes = (size_t)(2 * half_bytes);
     for (int k = 0; k < 2; ++k) {
         if (hipMalloc(&c->f[k], fbytes) != hipSuccess) {
             c->f[k] = nullptr;
@@ -635,7 +643,7 @@ int lbm_get_populations(lbm_ctx *c, double *f, int on_device) {
         (void)hipGetLastError();
         return fail(c, LBM_ENOMEM, "cannot allocate the population staging buffer");
     }
-    hipError_t e = lbm::launch_get_pops(c->p.prec, c->f[c->cur], c->links, c->idx, dst, c->p.nx, c->p.ny, c->p.nz, c->plane,
+    hipError_t e = lbm::launch_get_pops(c->p.prec, c->f[c->cur], c->links, c->idx, dst, c->p.nx, c->p.ny, c->p.nz, c->ngroups,
                                         c->ref, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess && !on_device) e = hipMemcpy(f, dst, bytes, hipMemcpyDeviceToHost);
@@ -659,7 +667,7 @@ int lbm_set_populations(lbm_ctx *c, const double *f, int on_device) {
             return fail(c, LBM_EDEVICE, "set_populations: copy failed");
         }
     }
-    hipError_t e = lbm::launch_set_pops(c->p.prec, c->f[c->cur], c->links, c->idx, src, c->p.nx, c->p.ny, c->p.nz, c->plane,
+    hipError_t e = lbm::launch_set_pops(c->p.prec, c->f[c->cur], c->links, c->idx, src, c->p.nx, c->p.ny, c->p.nz, c->ngroups,
                                         c->ref, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (!on_device) (void)hipFree(src);

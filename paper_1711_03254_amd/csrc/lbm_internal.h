@@ -19,6 +19,18 @@ enum Mode : int {
     MODE_REDUCE = 3,   // no advance: FP64 block sums only
 };
 
+// Population storage.  Fluid sites have slot indices k; kGroup consecutive
+// slots form a group.  A buffer has two halves, directions 0 .. kSplit - 1
+// and kSplit .. 18 (each opposite pair inside one half).  In its half, the
+// component pair (f^1_i, f^2_i) of direction i (i - kSplit in the second
+// half) of slot k is pair number
+//   ((k / kGroup) * kHalfDirs + i_half) * kGroup + k % kGroup,
+// so the directions of a group lie in two short runs of memory, and a run
+// of kGroup slots of one direction is contiguous.
+constexpr int kGroup = 32;
+constexpr int kHalfDirs = 11;
+constexpr int kSplit = 11;
+
 // Per-block partial sums written by MODE_CHECK / MODE_REDUCE:
 // [rho1, rho2, rho uF_x, rho uF_y, rho uF_z, non-finite count, 0, 0].
 constexpr int kPartialStride = 8;
@@ -32,8 +44,7 @@ struct StepLaunch {
     const int32_t *wstart;  // work list bounds: per tile column (ty ntx + tx) nz + 1 entries
     const uint16_t *wpos;   // work list entries: tile positions ly tile_x + lx of fluid sites
     int nx, ny, nz;
-    int64_t plane;          // sites per direction plane (fluid sites plus padding); a plane holds
-                            // the pairs (component 1, component 2) of those sites
+    int64_t ngroups;        // slot groups per buffer half (fluid sites' groups plus padding)
     int tile_x, tile_y, zchunk;
     int ntx, nty, nzc;      // tiles in x, y and chunks in z
     double tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
@@ -50,16 +61,16 @@ hipError_t launch_finalize(const double *partials, int nblocks, double *out, hip
 hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, int nz, hipStream_t s);
 // Internal state from fields: f*_j(x) = f_eq,j(x + c_j) if that site is fluid,
 // else f_eq,opp(j)(x); f_eq from rho (2N), u (3N or null).  Populations of
-// fluid site s are at compact index idx[s] of each plane.
+// fluid site s are at slot idx[s].
 hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
-                              const double *rho1, const double *u, int nx, int ny, int nz, int64_t plane,
+                              const double *rho1, const double *u, int nx, int ny, int nz, int64_t ngroups,
                               int eq_kind, const double ref[2], hipStream_t s);
 // Internal state from ABI populations (inverse of the pull).
 hipError_t launch_set_pops(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *f, int nx,
-                           int ny, int nz, int64_t plane, const double ref[2], hipStream_t s);
+                           int ny, int nz, int64_t ngroups, const double ref[2], hipStream_t s);
 // ABI populations from the internal state (the pull); solid sites read 0.
 hipError_t launch_get_pops(int prec, const void *src, const uint32_t *links, const int32_t *idx, double *f, int nx,
-                           int ny, int nz, int64_t plane, const double ref[2], hipStream_t s);
+                           int ny, int nz, int64_t ngroups, const double ref[2], hipStream_t s);
 // Batched launches over many domains: a descriptor per domain (the typed
 // kernel arguments, built by fill_batch_desc from a StepLaunch) and a work list
 // of (domain, tile) pairs; flip swaps each descriptor's (src, dst).

@@ -116,7 +116,7 @@ struct KArgs {
     const int32_t *wstart;  // work list bounds per tile column and plane
     const uint16_t *wpos;   // work list entries: tile positions of the fluid sites
     int nx, ny, nz, ntx, nty, zchunk;
-    uint32_t plane_bytes;   // bytes of one direction's plane of component pairs
+    uint32_t half_bytes;    // bytes of one buffer half (directions 0-10 or 11-18)
     C tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
     int eq_kind, force_kind, wall_kind;
     double *partials;
@@ -124,30 +124,43 @@ struct KArgs {
     int64_t n_sites;
 };
 
+// Read-only tables of a launch, addressed as constant memory so that uniform
+// reads of them go through the scalar unit.
+typedef __attribute__((address_space(4))) const int32_t cint32;
+
 __device__ __forceinline__ int wrap(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
 }
 
-// Raw buffer access.  A population plane holds, per compact site index k,
-// the pair (f^1_i, f^2_i) of the two components, so one access moves both.
-// Two buffer resources cover a buffer: planes 0-10 and planes 11-18 (each
-// opposite pair within one); the scalar offset selects the plane and the
-// 32-bit lane offset the site.  Every access issued is in bounds (lanes
-// without work are masked off), so the range check never applies.
+// Raw buffer access.  A population pair (f^1_i, f^2_i) of the two
+// components moves in one access.  Two buffer resources cover a buffer, one
+// per half (directions 0-10 and 11-18, each opposite pair within one); the
+// 32-bit lane offset selects the slot (group_off) and the scalar or
+// immediate offset the direction (kGroup pairs per direction run).  Every
+// access issued is in bounds (lanes without work are masked off), so the
+// range check never applies.
 constexpr int kRsrcWord3 = 0x00020000;   // gfx9 raw (unswizzled) buffer
 constexpr int kNonTemporal = 2;          // cache policy of the population stores
-constexpr int kSplit = 11;               // first plane of the second resource
+
+// Byte offset of slot k within a buffer half, and the offset of direction i
+// (its run within the group) for pairs of pb bytes.
+__host__ __device__ constexpr uint32_t group_off(uint32_t k, uint32_t pb) {
+    return ((k / kGroup) * (uint32_t)(kHalfDirs * kGroup) + k % kGroup) * pb;
+}
+__host__ __device__ constexpr uint32_t dir_off(int i, uint32_t pb) {
+    return (uint32_t)(i < kSplit ? i : i - kSplit) * (uint32_t)kGroup * pb;
+}
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t half_rsrc(const void *base, int h, uint32_t pb) {
-    char *p = const_cast<char *>(static_cast<const char *>(base)) + (h ? (size_t)kSplit * pb : 0);
-    return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)((h ? 19 - kSplit : kSplit) * pb), kRsrcWord3);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t half_rsrc(const void *base, int h, uint32_t half_bytes) {
+    char *p = const_cast<char *>(static_cast<const char *>(base)) + (h ? (size_t)half_bytes : 0);
+    return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)half_bytes, kRsrcWord3);
 }
 
-// Loads the pair of plane-relative byte offset v + s.  The loaded vector is
+// Loads the pair at byte offset v + s of a half.  The loaded vector is
 // reinterpreted as a whole (an integer or a struct) before it is split:
 // extracting its elements one by one lets the compiler narrow the load to
 // its first element.
@@ -294,76 +307,130 @@ struct CompState {
 // 4.5 cu^2 - 1.5 u^2; r2 is 1 for R2, else 0).  Each opposite pair shares
 // the part E even under c -> -c and the odd part O:
 // f*_i = w (E + O), f*_opp(i) = w (E - O), with P_i split the same way
-// (peven, podd per pair).  The terms are scaled by the weights up front and
-// only the non-zero components of c_i enter; 16-bit storage subtracts
-// w_i ref here.
+// (peven, podd per pair).  A component keeps only X, tr X, F and rho; each
+// pair's terms are formed from them where the pair is stored (fewer live
+// registers than holding all weighted terms), with only the non-zero
+// components of c_i.  16-bit storage subtracts w_i ref here.
 template <typename C>
-struct Collide {
-    C f0;                                    // the rest population
-    C Ax, Ay, Az;                            // axis pairs: 4.5 w (X_aa - t) - w ref
-    C Dxy, Dxz, Dyz, Qxy, Qxz, Qyz;          // diagonal pairs: 4.5 w (X_aa + X_bb - t) - w ref, 4.5 w X_ab
-    C F18x, F18y, F18z, F36x, F36y, F36z;    // 1.5 w F
-    C r18, r36;                              // w rho
+struct Relaxed {
+    C xx, yy, zz, xy, xz, yz, tr;   // X and its trace
+    C Fx, Fy, Fz, rho, ref;
 };
 
 template <typename C>
-__device__ __forceinline__ Collide<C> collide_prep(const CompState<C> &st, C ux, C uy, C uz, C r2, C keep, C guo,
-                                                   C pe0) {
+__device__ __forceinline__ Relaxed<C> relax(C rho, C Fx, C Fy, C Fz, const Moments<C> &m, C ux, C uy, C uz, C r2,
+                                            C keep, C guo, C ref) {
     constexpr C T0 = C(1.0 / 3.0);
-    const Moments<C> &m = *st.m;
-    const C rho = st.rho, Fx = st.Fx, Fy = st.Fy, Fz = st.Fz;
     // X: the non-equilibrium flux of Eq. (10) relaxed by 1 - 1/tau, plus the
     // second-order forcing part.
     const C rt = rho * T0, ru = r2 * rho;
     const C g2 = C(2) * guo;
-    const C Xxx = keep * (m.xx - rt - ru * ux * ux) + g2 * ux * Fx;
-    const C Xyy = keep * (m.yy - rt - ru * uy * uy) + g2 * uy * Fy;
-    const C Xzz = keep * (m.zz - rt - ru * uz * uz) + g2 * uz * Fz;
-    const C Xxy = keep * (m.xy - ru * ux * uy) + guo * (ux * Fy + Fx * uy);
-    const C Xxz = keep * (m.xz - ru * ux * uz) + guo * (ux * Fz + Fx * uz);
-    const C Xyz = keep * (m.yz - ru * uy * uz) + guo * (uy * Fz + Fy * uz);
-    const C tr = Xxx + Xyy + Xzz;
-    const C t = T0 * tr;
-    const C ref = st.ref;
-    const C ref18 = ref * C(1.0 / 18.0), ref36 = ref * C(1.0 / 36.0);
-    Collide<C> c;
-    c.f0 = C(1.0 / 3.0) * (rho * pe0 - ref) - C(0.5) * tr;   // w_0 = 1/3, c = 0
-    c.Ax = C(0.25) * (Xxx - t) - ref18;
-    c.Ay = C(0.25) * (Xyy - t) - ref18;
-    c.Az = C(0.25) * (Xzz - t) - ref18;
-    c.Dxy = C(0.125) * (Xxx + Xyy - t) - ref36;
-    c.Dxz = C(0.125) * (Xxx + Xzz - t) - ref36;
-    c.Dyz = C(0.125) * (Xyy + Xzz - t) - ref36;
-    c.Qxy = C(0.25) * Xxy;
-    c.Qxz = C(0.25) * Xxz;
-    c.Qyz = C(0.25) * Xyz;
-    c.F18x = Fx * C(1.0 / 12.0); c.F18y = Fy * C(1.0 / 12.0); c.F18z = Fz * C(1.0 / 12.0);
-    c.F36x = Fx * C(1.0 / 24.0); c.F36y = Fy * C(1.0 / 24.0); c.F36z = Fz * C(1.0 / 24.0);
-    c.r18 = rho * C(1.0 / 18.0);
-    c.r36 = rho * C(1.0 / 36.0);
-    return c;
+    Relaxed<C> x;
+    x.xx = keep * (m.xx - rt - ru * ux * ux) + g2 * ux * Fx;
+    x.yy = keep * (m.yy - rt - ru * uy * uy) + g2 * uy * Fy;
+    x.zz = keep * (m.zz - rt - ru * uz * uz) + g2 * uz * Fz;
+    x.xy = keep * (m.xy - ru * ux * uy) + guo * (ux * Fy + Fx * uy);
+    x.xz = keep * (m.xz - ru * ux * uz) + guo * (ux * Fz + Fx * uz);
+    x.yz = keep * (m.yz - ru * uy * uz) + guo * (uy * Fz + Fy * uz);
+    x.tr = x.xx + x.yy + x.zz;
+    x.Fx = Fx;
+    x.Fy = Fy;
+    x.Fz = Fz;
+    x.rho = rho;
+    x.ref = ref;
+    return x;
+}
+
+// f*_0 (w_0 = 1/3, c = 0).
+template <typename C>
+__device__ __forceinline__ C collide_rest(const Relaxed<C> &x, C pe0) {
+    return C(1.0 / 3.0) * (x.rho * pe0 - x.ref) - C(0.5) * x.tr;
 }
 
 // f*_i and f*_opp(i) of the opposite pair k (odd member i = 2k + 1).
 template <int k, typename C>
-__device__ __forceinline__ void collide_pair(const Collide<C> &c, C podd, C peven, C &plus, C &minus) {
+__device__ __forceinline__ void collide_pair(const Relaxed<C> &x, C podd, C peven, C &plus, C &minus) {
     constexpr int i = 2 * k + 1;
     constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+    const C t = C(1.0 / 3.0) * x.tr;
     C ew, ow;   // w E and w O
     if constexpr (i <= 6) {
-        const C A = X != 0 ? c.Ax : (Y != 0 ? c.Ay : c.Az);
-        const C Fa = X != 0 ? c.F18x : (Y != 0 ? c.F18y : c.F18z);
-        ew = c.r18 * peven + A;
-        ow = c.r18 * podd + Fa;   // c_a = +1 for the odd member
+        const C Xaa = X != 0 ? x.xx : (Y != 0 ? x.yy : x.zz);
+        const C ref18 = x.ref * C(1.0 / 18.0);
+        const C A = C(0.25) * (Xaa - t) - ref18;
+        const C Fa = (X != 0 ? x.Fx : (Y != 0 ? x.Fy : x.Fz)) * C(1.0 / 12.0);
+        const C r18 = x.rho * C(1.0 / 18.0);
+        ew = r18 * peven + A;
+        ow = r18 * podd + Fa;   // c_a = +1 for the odd member
     } else {
-        const C D = (X != 0 && Y != 0) ? c.Dxy : (X != 0 ? c.Dxz : c.Dyz);
-        const C Q = (X != 0 && Y != 0) ? c.Qxy : (X != 0 ? c.Qxz : c.Qyz);
+        const C Xaa = X != 0 ? x.xx : x.yy;
+        const C Xbb = Z != 0 ? x.zz : x.yy;
+        const C Xab = (X != 0 && Y != 0) ? x.xy : (X != 0 ? x.xz : x.yz);
+        const C ref36 = x.ref * C(1.0 / 36.0);
+        const C D = C(0.125) * (Xaa + Xbb - t) - ref36;
+        const C Q = C(0.25) * Xab;
         constexpr int sg = X * Y + X * Z + Y * Z;   // product of the two non-zero components
-        ew = c.r36 * peven + (sg > 0 ? D + Q : D - Q);
-        ow = c.r36 * podd + dot_signed<X, Y, Z>(c.F36x, c.F36y, c.F36z);
+        const C F36x = x.Fx * C(1.0 / 24.0), F36y = x.Fy * C(1.0 / 24.0), F36z = x.Fz * C(1.0 / 24.0);
+        const C r36 = x.rho * C(1.0 / 36.0);
+        ew = r36 * peven + (sg > 0 ? D + Q : D - Q);
+        ow = r36 * podd + dot_signed<X, Y, Z>(F36x, F36y, F36z);
     }
     plus = ew + ow;
     minus = ew - ow;
+}
+
+// The collision of both components of a site (Eqs. 3, 5-6, 9, 10 and the
+// forcing term), in two parts: collide_prepare relaxes the second moments
+// (Eqs. 5-6 with p = rho_1 / rho: tau_mix is linear in p, so
+// 1/tau = rho / (rho_1 tau_1 + rho_2 tau_2)); collide_emit forms the 19
+// pairs and stores them at byte offset vo of each plane of the destination.
+template <typename C>
+struct SiteCollide {
+    Relaxed<C> x0, x1;
+    C ux, uy, uz, usq, pe0, r2;
+};
+
+template <typename S, typename C>
+__device__ __forceinline__ SiteCollide<C> collide_prepare(const KArgs<S> &a, const C (&rho)[2], const C (&Fx)[2],
+                                                          const C (&Fy)[2], const C (&Fz)[2], const Moments<C> (&m)[2],
+                                                          C ux, C uy, C uz, C sref0, C sref1) {
+    SiteCollide<C> sc;
+    const C rho_t = rho[0] + rho[1];
+    sc.usq = ux * ux + uy * uy + uz * uz;
+    const C omega = rho_t * recip(rho[0] * a.tau0 + rho[1] * a.tau1);
+    const C keep = C(1) - omega;
+    const C guo = a.force_kind == 0 ? C(1) - C(0.5) * omega : C(0);
+    sc.r2 = a.eq_kind == 1 ? C(1) : C(0);
+    sc.pe0 = C(1) - sc.r2 * C(1.5) * sc.usq;
+    sc.x0 = relax(rho[0], Fx[0], Fy[0], Fz[0], m[0], ux, uy, uz, sc.r2, keep, guo, sref0);
+    sc.x1 = relax(rho[1], Fx[1], Fy[1], Fz[1], m[1], ux, uy, uz, sc.r2, keep, guo, sref1);
+    sc.ux = ux;
+    sc.uy = uy;
+    sc.uz = uz;
+    return sc;
+}
+
+template <typename S, typename C>
+__device__ __forceinline__ void collide_emit(const SiteCollide<C> &sc, __amdgpu_buffer_rsrc_t dstA,
+                                             __amdgpu_buffer_rsrc_t dstB, uint32_t vo) {
+    auto put = [&](auto I, C v0, C v1) {
+        constexpr int i = I;
+        pair_store<S>(Codec<S>::st(v0), Codec<S>::st(v1), i < kSplit ? dstA : dstB, vo, dir_off(i, 2 * sizeof(S)));
+    };
+    put(std::integral_constant<int, 0>{}, collide_rest(sc.x0, sc.pe0), collide_rest(sc.x1, sc.pe0));
+    sfor<9>([&](auto K) {
+        constexpr int k = K;
+        constexpr int i = 2 * k + 1;
+        // The even and odd parts of P_i, shared by the two components.
+        const C cu = dot_signed<cx_of(i), cy_of(i), cz_of(i)>(sc.ux, sc.uy, sc.uz);
+        const C podd = cu * (C(3) + C(4.5) * (cu * cu - sc.usq));
+        const C peven = sc.pe0 + sc.r2 * C(4.5) * cu * cu;
+        C p0, m0, p1, m1;
+        collide_pair<k>(sc.x0, podd, peven, p0, m0);
+        collide_pair<k>(sc.x1, podd, peven, p1, m1);
+        put(std::integral_constant<int, 2 * k + 1>{}, p0, p1);
+        put(std::integral_constant<int, 2 * k + 2>{}, m0, m1);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -397,13 +464,12 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     constexpr int NE = (HW * HH + NT - 1) / NT; // index-tile entries per thread
     constexpr int NR = 2 * RW + 2 * TY;         // ring sites of the tile
     static_assert(NR <= NT, "the ring must fit in the block");
-    constexpr uint32_t ESZ = sizeof(S);
 
     // Densities of both components per site, side by side: one LDS access
     // moves a neighbour's pair.
     struct alignas(2 * sizeof(C)) PsiPair { C a, b; };
     __shared__ PsiPair psi[4][RH][RW];
-    // byte offset of each site's population pair within a plane, -1 where solid
+    // byte offset (group_off) of each site's population pairs, -1 where solid
     __shared__ int kid[6][HH][HW];
     __shared__ double red[NT / 64][6];
 
@@ -417,7 +483,9 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     const int tid = threadIdx.x;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
-    const uint32_t pb = a.plane_bytes;
+    const uint32_t hb = a.half_bytes;
+    constexpr uint32_t PB = 2 * sizeof(S);      // bytes of a component pair
+    constexpr uint32_t DS = kGroup * PB;        // from one direction's run to the next
 
     // Ring position j (0 <= j < NR) in index-tile coordinates: the rows
     // above and below the tile, then its left and right columns.
@@ -444,7 +512,10 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     // to wstart[... + z + 1] of wpos, the tile positions (ly TX + lx) of the
     // plane's fluid sites in storage order (positions beyond the lattice edge
     // stand for their periodic images and are pulled but not stored).
-    const int32_t *ws = a.wstart + (size_t)(ty * a.ntx + tx) * (nz + 1);
+    // The bounds are uniform and read through the scalar unit (the constant
+    // address space: they do not change during the launch), so waiting for
+    // them does not wait for the vector stores still in flight.
+    const cint32 *ws = (const cint32 *)(a.wstart + (size_t)(ty * a.ntx + tx) * (nz + 1));
     auto fetch_work = [&](int zq, int &cnt, int &pos) {
         const int zz = wrap(zq, nz);
         const int w0 = ws[zz];
@@ -475,10 +546,10 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     auto store_idx = [&](int q, const int (&v)[NE]) {
 #pragma unroll
         for (int j = 0; j < NE; ++j)
-            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? v[j] * (int)(2 * ESZ) : -1;
+            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? (int)group_off((uint32_t)v[j], PB) : -1;
     };
 
-    const __amdgpu_buffer_rsrc_t srcA = half_rsrc(a.src, 0, pb), srcB = half_rsrc(a.src, 1, pb);
+    const __amdgpu_buffer_rsrc_t srcA = half_rsrc(a.src, 0, hb), srcB = half_rsrc(a.src, 1, hb);
 
     // Pull of the site at index-tile position (hr, hc) whose populations sit
     // at byte offset self, planes zw - 1, zw, zw + 1 in index slots qm, q0,
@@ -487,11 +558,11 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     // (the scalar offset), so the bounce-back is a select of lane offsets.
     using R = typename Codec<S>::R;
     auto issue = [&](int hr, int hc, int qm, int q0, int qp, uint32_t self, R (&raw)[2][19]) {
-        const uint32_t self_p = self + pb;
+        const uint32_t self_p = self + DS;
         sfor<19>([&](auto I) {
             constexpr int i = I;
             constexpr int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-            const uint32_t soff = (uint32_t)(lo < kSplit ? lo : lo - kSplit) * pb;
+            const uint32_t soff = dir_off(lo, PB);
             uint32_t off;
             if constexpr (i == 0) {
                 off = self;
@@ -500,7 +571,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                 const int q = Z == 0 ? q0 : (Z > 0 ? qm : qp);   // plane zw - Z
                 const int nb = kid[q][hr - Y][hc - X];
                 if constexpr (i == lo) off = nb >= 0 ? (uint32_t)nb : self_p;
-                else off = nb >= 0 ? (uint32_t)nb + pb : self;
+                else off = nb >= 0 ? (uint32_t)nb + DS : self;
             }
             pair_load<S>(lo < kSplit ? srcA : srcB, off, soff, raw[0][i], raw[1][i]);
         });
@@ -511,7 +582,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     for (int d = 0; d < 2; ++d) mn[d] = Moments<C>{C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
     // this lane's work-list site of the plane to collide (c) / of the next plane (n)
     bool fluid_c = false, fluid_n = false;
-    int kc = 0, kn = 0;          // byte offsets of its populations within a plane
+    int kc = 0, kn = 0;          // byte offsets (group_off) of its populations
     int pc = 0, pn = 0;          // tile positions ly TX + lx
     int wcnt = 0, wpos = 0;      // work list of the plane to pull next (prefetched)
     const C ref0 = a.ref0, ref1 = a.ref1;
@@ -630,7 +701,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     pc = pn;
     __syncthreads();
 
-    const __amdgpu_buffer_rsrc_t dstA = half_rsrc(a.dst, 0, pb), dstB = half_rsrc(a.dst, 1, pb);
+    const __amdgpu_buffer_rsrc_t dstA = half_rsrc(a.dst, 0, hb), dstB = half_rsrc(a.dst, 1, hb);
 
     for (int z = z0; z < z1; ++z) {
         const int sm = (z - z0) & 3, s0 = (z - z0 + 1) & 3, sp = (z - z0 + 2) & 3;
@@ -700,7 +771,6 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
             const C ux = (mc[0].jx + mc[1].jx + C(0.5) * (Fx[0] + Fx[1])) * inv;
             const C uy = (mc[0].jy + mc[1].jy + C(0.5) * (Fy[0] + Fy[1])) * inv;
             const C uz = (mc[0].jz + mc[1].jz + C(0.5) * (Fz[0] + Fz[1])) * inv;
-            const C usq = ux * ux + uy * uy + uz * uz;
 
             if constexpr (MODE == MODE_CHECK || MODE == MODE_MOMENTS) {
                 const bool ok = isfinite(rho[0]) && isfinite(rho[1]) && isfinite(ux) && isfinite(uy) && isfinite(uz);
@@ -723,44 +793,9 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
             }
 
             if constexpr (MODE == MODE_STEP || MODE == MODE_CHECK) {
-                // Eqs. (5)-(6) with p = rho_1 / rho: tau_mix is linear in p,
-                // so 1/tau = rho / (rho_1 tau_1 + rho_2 tau_2).
-                const C omega = rho_t * recip(rho[0] * a.tau0 + rho[1] * a.tau1);
-                const C keep = C(1) - omega;
-                const C guo = a.force_kind == 0 ? C(1) - C(0.5) * omega : C(0);
-
-                // The even and odd parts of P_i per opposite pair, shared by
-                // the two components.
-                const C r2 = a.eq_kind == 1 ? C(1) : C(0);
-                const C pe0 = C(1) - r2 * C(1.5) * usq;
-                C podd[9], peven[9];
-                sfor<9>([&](auto K) {
-                    constexpr int i = 2 * K + 1;
-                    const C cu = dot_signed<cx_of(i), cy_of(i), cz_of(i)>(ux, uy, uz);
-                    podd[K] = cu * (C(3) + C(4.5) * (cu * cu - usq));
-                    peven[K] = pe0 + r2 * C(4.5) * cu * cu;
-                });
-
-                const uint32_t vo = (uint32_t)kc;
-                auto put = [&](auto I, C v0, C v1) {
-                    constexpr int i = I;
-                    pair_store<S>(Codec<S>::st(v0), Codec<S>::st(v1), i < kSplit ? dstA : dstB, vo,
-                                  (uint32_t)(i < kSplit ? i : i - kSplit) * pb);
-                };
                 const C sref0 = Codec<S>::shifted ? ref0 : C(0), sref1 = Codec<S>::shifted ? ref1 : C(0);
-                const CompState<C> st0{rho[0], Fx[0], Fy[0], Fz[0], &mc[0], sref0};
-                const CompState<C> st1{rho[1], Fx[1], Fy[1], Fz[1], &mc[1], sref1};
-                const Collide<C> c0 = collide_prep(st0, ux, uy, uz, r2, keep, guo, pe0);
-                const Collide<C> c1 = collide_prep(st1, ux, uy, uz, r2, keep, guo, pe0);
-                put(std::integral_constant<int, 0>{}, c0.f0, c1.f0);
-                sfor<9>([&](auto K) {
-                    constexpr int k = K;
-                    C p0, m0, p1, m1;
-                    collide_pair<k>(c0, podd[k], peven[k], p0, m0);
-                    collide_pair<k>(c1, podd[k], peven[k], p1, m1);
-                    put(std::integral_constant<int, 2 * k + 1>{}, p0, p1);
-                    put(std::integral_constant<int, 2 * k + 2>{}, m0, m1);
-                });
+                collide_emit<S>(collide_prepare(a, rho, Fx, Fy, Fz, mc, ux, uy, uz, sref0, sref1), dstA, dstB,
+                                (uint32_t)kc);
             }
         }
 
@@ -790,14 +825,506 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// The fused step at 32- and 16-bit storage, software-pipelined along z.
+// ---------------------------------------------------------------------------
+// A pulled opposite-pair member as loaded: both components' values of one
+// direction, 64 bits at FP32, 32 bits (two halves) at 16 bits.  Held packed
+// until its moments are taken, so a plane's pulls occupy 38 registers at
+// FP32 and 19 at 16 bits while they are in flight.
+template <typename S> struct Held;
+template <> struct Held<float> { using T = uint64_t; };
+template <> struct Held<__half> { using T = uint32_t; };
+template <> struct Held<__hip_bfloat16> { using T = uint32_t; };
+
+template <typename S>
+__device__ __forceinline__ typename Held<S>::T held_load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    if constexpr (std::is_same_v<S, float>)
+        return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+    else
+        return __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0);
+}
+
+// Component D (0 or 1) of a held pair, as FP32.
+template <typename S, int D>
+__device__ __forceinline__ float held_comp(typename Held<S>::T x) {
+    if constexpr (std::is_same_v<S, float>) {
+        return __builtin_bit_cast(float, (uint32_t)(D == 0 ? x : x >> 32));
+    } else if constexpr (std::is_same_v<S, __half>) {
+        return __half2float(__builtin_bit_cast(__half, (unsigned short)(D == 0 ? x & 0xffffu : x >> 16)));
+    } else {
+        return __builtin_bit_cast(float, D == 0 ? x << 16 : x & 0xffff0000u);
+    }
+}
+
+// Eq. (4) and the second moments of component D of a held pull, summed in
+// the order of moments_of (the pair sums and differences of the nine
+// opposite pairs), with the 16-bit shift added back.
+template <typename S, int D>
+__device__ __forceinline__ Moments<float> held_moments(const typename Held<S>::T (&raw)[19], float ref) {
+    const float z = -0.0f;
+    Moments<float> m{z, z, z, z, z, z, z, z, z, z};
+    m.r = held_comp<S, D>(raw[0]);
+    sfor<9>([&](auto K) {
+        constexpr int i = 2 * K + 1;
+        constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+        const float p = held_comp<S, D>(raw[i]), q = held_comp<S, D>(raw[i + 1]);
+        const float s = p + q, d = p - q;
+        m.r += s;
+        acc_signed<X>(m.jx, d);
+        acc_signed<Y>(m.jy, d);
+        acc_signed<Z>(m.jz, d);
+        acc_signed<X * X>(m.xx, s);
+        acc_signed<Y * Y>(m.yy, s);
+        acc_signed<Z * Z>(m.zz, s);
+        acc_signed<X * Y>(m.xy, s);
+        acc_signed<X * Z>(m.xz, s);
+        acc_signed<Y * Z>(m.yz, s);
+    });
+    if constexpr (Codec<S>::shifted) {
+        const float t = (1.0f / 3.0f) * ref;
+        m.r += ref;
+        m.xx += t;
+        m.yy += t;
+        m.zz += t;
+    }
+    return m;
+}
+
+// The density of component D alone, in the same order (same bits).
+template <typename S, int D>
+__device__ __forceinline__ float held_density(const typename Held<S>::T (&raw)[19], float ref) {
+    float r = held_comp<S, D>(raw[0]);
+    sfor<9>([&](auto K) {
+        constexpr int i = 2 * K + 1;
+        r += held_comp<S, D>(raw[i]) + held_comp<S, D>(raw[i + 1]);
+    });
+    if constexpr (Codec<S>::shifted) r += ref;
+    return r;
+}
+
+// What the collision of a site needs from its pulled populations besides
+// the densities (which the LDS plane holds): the mixture momentum j_1 + j_2
+// and each component's second moments.
+struct SiteMoments {
+    float jx, jy, jz;
+    Moments<float> m[2];   // only the second moments (xx .. yz) are used
+};
+
+// One block's work at 32- and 16-bit storage: as step_body, but with the
+// pulls of plane z + 2 issued before the collision of plane z, so that the
+// next plane's loads are in flight while the collision computes and stores.
+// Iteration z:
+//   D  issue the pulls of plane z + 2 (one job per lane), the index tile of
+//      plane z + 4 and this lane's work-list entry of plane z + 3;
+//   E  collide plane z and store;
+//   A  consume the pulls of plane z + 2: moments of its sites, densities of
+//      the plane and its ring into LDS; ring jobs beyond one pass (dense
+//      tiles only) are pulled here, one round trip each; stage the index
+//      tile of plane z + 4;
+//   B  barrier.
+// LDS slots: densities of planes z - 1 .. z + 2 (four: E of plane z reads
+// z - 1 .. z + 1 while a faster wave's A writes z + 2), index tiles of
+// planes z - 1 .. z + 4 (six); each slot is rewritten only after a barrier
+// that follows its last read.
+template <typename S, int TX, int TY, int MODE>
+__device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slot) {
+    using C = float;
+    using H = typename Held<S>::T;
+    constexpr int NT = TX * TY;
+    constexpr int RW = TX + 2, RH = TY + 2;     // density tile with its ring
+    constexpr int HW = TX + 4, HH = TY + 4;     // index tile with a ring of two
+    constexpr int NE = (HW * HH + NT - 1) / NT; // index-tile entries per thread
+    constexpr int NR = 2 * RW + 2 * TY;         // ring sites of the tile
+    static_assert(NR <= NT, "the ring must fit in the block");
+
+    struct alignas(8) PsiPair { C a, b; };
+    __shared__ PsiPair psi[4][RH][RW];
+    __shared__ int kid[6][HH][HW];
+    __shared__ double red[NT / 64][6];
+    // j_1 + j_2 and both components' second moments of this lane's site of
+    // the plane to collide (written by the lane itself one plane earlier)
+    __shared__ float mom[15][NT];
+
+    const int tx = b % a.ntx;
+    b /= a.ntx;
+    const int ty = b % a.nty;
+    const int zc = b / a.nty;
+    const int z0 = zc * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.nz);
+
+    const int tid = threadIdx.x;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t hb = a.half_bytes;
+    constexpr uint32_t PB = 2 * sizeof(S);      // bytes of a component pair
+    constexpr uint32_t DS = kGroup * PB;        // from one direction's run to the next
+    const int tly = tid / TX, tlx = tid % TX;
+
+    auto ring_pos = [&](int j, int &hr, int &hc) {
+        if (j < RW) { hr = 1; hc = 1 + j; }
+        else if (j < 2 * RW) { hr = RH; hc = 1 + j - RW; }
+        else if (j < 2 * RW + TY) { hr = 2 + j - 2 * RW; hc = 1; }
+        else { hr = 2 + j - 2 * RW - TY; hc = RW; }
+    };
+    // Job j of a plane whose work list has cnt entries and gives this lane
+    // the tile position pos: a site (j < cnt), a ring position, or nothing.
+    auto job_at = [&](int j, int cnt, int pos, int &hr, int &hc) -> bool {
+        if (j < cnt) { hr = pos / TX + 2; hc = pos % TX + 2; return true; }
+        if (j - cnt < NR) { ring_pos(j - cnt, hr, hc); return true; }
+        return false;
+    };
+
+    // Work-list bounds (uniform; scalar reads) and this lane's entry.
+    const cint32 *ws = (const cint32 *)(a.wstart + (size_t)(ty * a.ntx + tx) * (nz + 1));
+    struct Bounds { int w0, cnt; };
+    auto bounds = [&](int zq) {
+        const int zz = wrap(zq, nz);
+        const int w0 = ws[zz];
+        return Bounds{w0, ws[zz + 1] - w0};
+    };
+    auto entry = [&](Bounds bd) { return tid < bd.cnt ? (int)a.wpos[bd.w0 + tid] : 0; };
+
+    uint32_t exy[NE];   // lattice (x, y) of the index-tile entries this thread stages
+    bool eok[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        const int e = tid + j * NT;
+        eok[j] = e < HW * HH;
+        const int er = e / HW, ec = e % HW;
+        exy[j] = (uint32_t)wrap(tx * TX - 2 + ec, nx) + (uint32_t)nx * (uint32_t)wrap(ty * TY - 2 + er, ny);
+    }
+    const __amdgpu_buffer_rsrc_t ridx = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int32_t *>(a.idx), 0, (int)(4u * (uint32_t)a.n_sites), kRsrcWord3);
+    auto fetch_idx = [&](int zq, int (&v)[NE]) {
+        const uint32_t zo = (uint32_t)wrap(zq, nz) * nxy * 4u;
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+            v[j] = -1;
+            if (eok[j]) v[j] = (int)__builtin_amdgcn_raw_buffer_load_b32(ridx, exy[j] * 4u, zo, 0);
+        }
+    };
+    auto kslot = [&](int p) { return (p - z0 + 2) % 6; };   // index slot of plane p >= z0 - 2
+    auto store_idx = [&](int p, const int (&v)[NE]) {
+        const int q = kslot(p);
+#pragma unroll
+        for (int j = 0; j < NE; ++j)
+            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? (int)group_off((uint32_t)v[j], PB) : -1;
+    };
+    auto psi_slot = [&](int p) { return (p - z0 + 1) & 3; };   // density slot of plane p >= z0 - 1
+
+    const __amdgpu_buffer_rsrc_t srcA = half_rsrc(a.src, 0, hb), srcB = half_rsrc(a.src, 1, hb);
+
+    // The 19 pair loads of the site at index-tile position (hr, hc) of plane
+    // zw (its populations at byte offset self): f_i = f*_i(x - c_i), or
+    // f*_opp(i)(x) when x - c_i is solid; both members of an opposite pair
+    // are addressed from the odd member's plane, so the bounce-back is a
+    // select of lane offsets.
+    auto issue = [&](int zw, int hr, int hc, uint32_t self, H (&raw)[19]) {
+        const int qm = kslot(zw - 1), q0 = kslot(zw), qp = kslot(zw + 1);
+        const uint32_t self_p = self + DS;
+        sfor<19>([&](auto I) {
+            constexpr int i = I;
+            constexpr int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+            const uint32_t soff = dir_off(lo, PB);
+            uint32_t off;
+            if constexpr (i == 0) {
+                off = self;
+            } else {
+                constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+                const int q = Z == 0 ? q0 : (Z > 0 ? qm : qp);   // plane zw - Z
+                const int nb = kid[q][hr - Y][hc - X];
+                if constexpr (i == lo) off = nb >= 0 ? (uint32_t)nb : self_p;
+                else off = nb >= 0 ? (uint32_t)nb + DS : self;
+            }
+            raw[i] = held_load<S>(lo < kSplit ? srcA : srcB, off, soff);
+        });
+    };
+    const C ref0 = a.ref0, ref1 = a.ref1;
+
+    // Densities (and, for a site job with want_mom, the moments) of a
+    // completed pull into the LDS plane of zw; ring positions without a
+    // fluid site take the wall densities.
+    auto consume = [&](int zw, bool is_site, bool is_job, int hr, int hc, int self, const H (&raw)[19],
+                       bool want_mom, SiteMoments &sm) {
+        C r0 = a.wall0, r1 = a.wall1;
+        if (self >= 0) {
+            if (is_site && want_mom) {
+                const Moments<C> m0 = held_moments<S, 0>(raw, ref0);
+                const Moments<C> m1 = held_moments<S, 1>(raw, ref1);
+                r0 = m0.r;
+                r1 = m1.r;
+                sm.jx = m0.jx + m1.jx;
+                sm.jy = m0.jy + m1.jy;
+                sm.jz = m0.jz + m1.jz;
+                sm.m[0] = m0;
+                sm.m[1] = m1;
+            } else {
+                r0 = held_density<S, 0>(raw, ref0);
+                r1 = held_density<S, 1>(raw, ref1);
+            }
+        }
+        if (is_job) psi[psi_slot(zw)][hr - 1][hc - 1] = PsiPair{r0, r1};
+    };
+    // Jobs of plane zw beyond the first pass (ring positions only: the
+    // tile's sites all fit in one pass), one round trip each; and the wall
+    // densities at the tile's solid sites.
+    auto finish_plane = [&](int zw, int cnt) {
+        for (int pass = 1; pass * NT < cnt + NR; ++pass) {
+            const int j = tid + pass * NT;
+            int hr = 0, hc = 0;
+            const bool is_job = job_at(j, cnt, 0, hr, hc);
+            const int self = is_job ? kid[kslot(zw)][hr][hc] : -1;
+            H raw[19];
+            if (self >= 0) issue(zw, hr, hc, (uint32_t)self, raw);
+            __builtin_amdgcn_sched_barrier(0);
+            SiteMoments unused;
+            consume(zw, false, is_job, hr, hc, self, raw, false, unused);
+        }
+        if (kid[kslot(zw)][tly + 2][tlx + 2] < 0)   // solid site of the tile: the wall densities
+            psi[psi_slot(zw)][tly + 1][tlx + 1] = PsiPair{a.wall0, a.wall1};
+    };
+
+    auto mom_put = [&](const SiteMoments &m) {
+        mom[0][tid] = m.jx;
+        mom[1][tid] = m.jy;
+        mom[2][tid] = m.jz;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            mom[3 + 6 * d][tid] = m.m[d].xx;
+            mom[4 + 6 * d][tid] = m.m[d].yy;
+            mom[5 + 6 * d][tid] = m.m[d].zz;
+            mom[6 + 6 * d][tid] = m.m[d].xy;
+            mom[7 + 6 * d][tid] = m.m[d].xz;
+            mom[8 + 6 * d][tid] = m.m[d].yz;
+        }
+    };
+    auto mom_get = [&](SiteMoments &m) {
+        m.jx = mom[0][tid];
+        m.jy = mom[1][tid];
+        m.jz = mom[2][tid];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            m.m[d].xx = mom[3 + 6 * d][tid];
+            m.m[d].yy = mom[4 + 6 * d][tid];
+            m.m[d].zz = mom[5 + 6 * d][tid];
+            m.m[d].xy = mom[6 + 6 * d][tid];
+            m.m[d].xz = mom[7 + 6 * d][tid];
+            m.m[d].yz = mom[8 + 6 * d][tid];
+        }
+    };
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    SiteMoments mc, mn;
+    {
+        const Moments<C> zm{C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
+        mc = SiteMoments{C(0), C(0), C(0), {zm, zm}};
+        mn = mc;
+    }
+    int kc = -1, pc = 0;   // the site job of the plane to collide: byte offset (-1: none), tile position
+    int kn = -1, pn = 0;   // ... of the next plane
+
+    // ---- prologue: index tiles of planes z0 - 2 .. z0 + 3; planes z0 - 1,
+    // z0 and z0 + 1 pulled, one round trip each.
+    {
+        int v[6][NE];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) fetch_idx(z0 - 2 + q, v[q]);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) store_idx(z0 - 2 + q, v[q]);
+    }
+    Bounds b2 = bounds(z0 + 2), b3 = bounds(z0 + 3);
+    int pos2 = entry(b2);
+    __syncthreads();
+    for (int q = 0; q < 3; ++q) {
+        const int zw = z0 - 1 + q;
+        const Bounds bd = bounds(zw);
+        const int pos = entry(bd);
+        int hr = 0, hc = 0;
+        const bool is_job = job_at(tid, bd.cnt, pos, hr, hc);
+        const int self = is_job ? kid[kslot(zw)][hr][hc] : -1;
+        H raw[19];
+        if (self >= 0) issue(zw, hr, hc, (uint32_t)self, raw);
+        __builtin_amdgcn_sched_barrier(0);
+        const bool is_site = tid < bd.cnt;
+        SiteMoments unused;
+        consume(zw, is_site, is_job, hr, hc, self, raw, q > 0, q == 1 ? mc : (q == 2 ? mn : unused));
+        if (q == 1) { kc = is_site ? self : -1; pc = pos; }
+        if (q == 2) { kn = is_site ? self : -1; pn = pos; }
+        finish_plane(zw, bd.cnt);
+    }
+    mom_put(mc);
+    __syncthreads();
+    // Nothing of the prologue stays in flight into the loop.
+    __builtin_amdgcn_s_waitcnt(0);
+
+    const __amdgpu_buffer_rsrc_t dstA = half_rsrc(a.dst, 0, hb), dstB = half_rsrc(a.dst, 1, hb);
+    int vnext[NE];
+
+    for (int z = z0; z < z1; ++z) {
+        const bool more = z + 2 <= z1;   // plane z + 2 is still needed (for the collision of z + 1)
+
+        // D: the pulls of plane z + 2 (the loads go out before this plane's
+        // stores)
+        H raw[19];
+        int self2 = -1, pos3 = 0;
+        Bounds b4{0, 0};
+        if (more) {
+            fetch_idx(z + 4, vnext);
+            pos3 = entry(b3);
+            b4 = bounds(z + 4);
+            int hr2 = 0, hc2 = 0;
+            const bool is_job = job_at(tid, b2.cnt, pos2, hr2, hc2);
+            self2 = is_job ? kid[kslot(z + 2)][hr2][hc2] : -1;
+            if (self2 >= 0) issue(z + 2, hr2, hc2, (uint32_t)self2, raw);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+
+        // E: collide plane z and store
+        const int sm_ = psi_slot(z - 1), s0 = psi_slot(z), sp = psi_slot(z + 1);
+        const int lx = pc % TX, ly = pc / TX;
+        const bool inside = tx * TX + lx < nx && ty * TY + ly < ny;   // not a periodic image
+        const bool collide = inside && kc >= 0;
+        if (collide) {
+            mom_get(mc);
+            const PsiPair here = psi[s0][ly + 1][lx + 1];
+            const C rho[2] = {here.a, here.b};
+
+            // Eqs. (7), (11): sum_i w_i c_i psi'(x + c_i) from the LDS planes.
+            const C nz0 = C(-0.0);
+            C n0x = nz0, n0y = nz0, n0z = nz0, n1x = nz0, n1y = nz0, n1z = nz0;
+            sfor<19>([&](auto I) {
+                constexpr int i = I;
+                if constexpr (i > 0) {
+                    constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+                    constexpr C wx = C(X * w_of(i)), wy = C(Y * w_of(i)), wz = C(Z * w_of(i));
+                    const int sl = Z == 0 ? s0 : (Z > 0 ? sp : sm_);
+                    const PsiPair pp = psi[sl][ly + 1 + Y][lx + 1 + X];
+                    const C p0 = pp.a, p1 = pp.b;
+                    if constexpr (X != 0) { n0x += wx * p0; n1x += wx * p1; }
+                    if constexpr (Y != 0) { n0y += wy * p0; n1y += wy * p1; }
+                    if constexpr (Z != 0) { n0z += wz * p0; n1z += wz * p1; }
+                }
+            });
+            C Fx[2], Fy[2], Fz[2];
+            Fx[0] = rho[0] * (a.G * n1x + a.gx);
+            Fy[0] = rho[0] * (a.G * n1y + a.gy);
+            Fz[0] = rho[0] * (a.G * n1z + a.gz);
+            Fx[1] = rho[1] * (a.G * n0x + a.gx);
+            Fy[1] = rho[1] * (a.G * n0y + a.gy);
+            Fz[1] = rho[1] * (a.G * n0z + a.gz);
+            if (a.wall_kind == 1) {
+                // Momentum-balanced walls: the wall part of the force on
+                // component a is G rho_a rho^s_b S with S = sum of w_i c_i over
+                // the solid neighbours x + c_i; each component gives up its
+                // share rho_a / rho of the sum over both components.
+                C Sx = C(-0.0), Sy = C(-0.0), Sz = C(-0.0);
+                sfor<19>([&](auto I) {
+                    constexpr int i = I;
+                    if constexpr (i > 0) {
+                        constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+                        const C sol = kid[kslot(z + Z)][ly + 2 + Y][lx + 2 + X] < 0 ? C(w_of(i)) : C(0);
+                        if constexpr (X != 0) Sx += C(X) * sol;
+                        if constexpr (Y != 0) Sy += C(Y) * sol;
+                        if constexpr (Z != 0) Sz += C(Z) * sol;
+                    }
+                });
+                const C net = a.G * (rho[0] * a.wall1 + rho[1] * a.wall0);
+                const C inv_t = recip(rho[0] + rho[1]);
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    const C share = rho[d] * inv_t * net;
+                    Fx[d] -= share * Sx;
+                    Fy[d] -= share * Sy;
+                    Fz[d] -= share * Sz;
+                }
+            }
+
+            // Eq. (8): u_F = (j_1 + j_2 + F / 2) / rho.
+            const C rho_t = rho[0] + rho[1];
+            const C inv = recip(rho_t);
+            const C ux = (mc.jx + C(0.5) * (Fx[0] + Fx[1])) * inv;
+            const C uy = (mc.jy + C(0.5) * (Fy[0] + Fy[1])) * inv;
+            const C uz = (mc.jz + C(0.5) * (Fz[0] + Fz[1])) * inv;
+
+            if constexpr (MODE == MODE_CHECK || MODE == MODE_MOMENTS) {
+                const bool ok = isfinite(rho[0]) && isfinite(rho[1]) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+                acc[0] += (double)rho[0];
+                acc[1] += (double)rho[1];
+                acc[2] += (double)rho_t * (double)ux;
+                acc[3] += (double)rho_t * (double)uy;
+                acc[4] += (double)rho_t * (double)uz;
+                acc[5] += ok ? 0.0 : 1.0;
+            }
+            if constexpr (MODE == MODE_MOMENTS) {
+                const uint32_t s = (uint32_t)(tx * TX + lx) + (uint32_t)nx * (uint32_t)(ty * TY + ly) + (uint32_t)z * nxy;
+                if (a.out_rho0) a.out_rho0[s] = (double)rho[0];
+                if (a.out_rho1) a.out_rho1[s] = (double)rho[1];
+                if (a.out_u) {
+                    a.out_u[s] = (double)ux;
+                    a.out_u[(size_t)a.n_sites + s] = (double)uy;
+                    a.out_u[2 * (size_t)a.n_sites + s] = (double)uz;
+                }
+            }
+            if constexpr (MODE == MODE_STEP || MODE == MODE_CHECK) {
+                const C sref0 = Codec<S>::shifted ? ref0 : C(0), sref1 = Codec<S>::shifted ? ref1 : C(0);
+                collide_emit<S>(collide_prepare(a, rho, Fx, Fy, Fz, mc.m, ux, uy, uz, sref0, sref1), dstA, dstB,
+                                (uint32_t)kc);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+
+        // A: the pulls of plane z + 2
+        mom_put(mn);
+        kc = kn;
+        pc = pn;
+        if (more) {
+            const bool is_site = tid < b2.cnt;
+            int hra = 0, hca = 0;
+            const bool is_job = job_at(tid, b2.cnt, pos2, hra, hca);
+            consume(z + 2, is_site, is_job, hra, hca, self2, raw, true, mn);
+            kn = is_site ? self2 : -1;
+            pn = pos2;
+            finish_plane(z + 2, b2.cnt);
+            store_idx(z + 4, vnext);
+            b2 = b3;
+            b3 = b4;
+            pos2 = pos3;
+        }
+        __syncthreads();   // B
+    }
+
+    if constexpr (MODE == MODE_CHECK || MODE == MODE_MOMENTS) {
+        const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double v = acc[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) red[wv][k] = v;
+        }
+        __syncthreads();
+        if (tid < 6) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NT / 64; ++q) s += red[q][tid];
+            a.partials[(size_t)slot * kPartialStride + tid] = s;
+        }
+    }
+}
+template <typename S, int TX, int TY, int MODE>
+__device__ __forceinline__ void step_dispatch(const KArgs<S> &a, int b, int slot) {
+    if constexpr (sizeof(S) == 8) step_body<S, TX, TY, MODE>(a, b, slot);
+    else step_body_pipe<S, TX, TY, MODE>(a, b, slot);
+}
+
 // Waves per SIMD the register allocator must allow: four for the 16-bit
 // instances (a few spilled registers cost less than a quarter of the waves,
 // and 1024-thread blocks need four), the natural count otherwise.
-template <typename S> constexpr int kMinWaves = sizeof(S) == 2 ? 4 : 1;
+template <typename S> constexpr int kMinWaves = sizeof(S) <= 4 ? 4 : 1;
 
 template <typename S, int TX, int TY, int MODE>
 __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(kMinWaves<S>))) step_kernel(KArgs<S> a) {
-    step_body<S, TX, TY, MODE>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
+    step_dispatch<S, TX, TY, MODE>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
 }
 
 // Many domains in one launch: work item w = (domain, tile) of a list sorted
@@ -812,7 +1339,7 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(kMi
         a.src = a.dst;
         a.dst = const_cast<S *>(t);
     }
-    step_body<S, TX, TY, MODE>(a, w.y, w.y);
+    step_dispatch<S, TX, TY, MODE>(a, w.y, w.y);
 }
 
 __global__ void finalize_kernel(const double *partials, int nblocks, double *out) {
@@ -885,24 +1412,32 @@ __device__ __forceinline__ double feq_dir(int i, double rho, double ux, double u
     return rho * w * br;
 }
 
-template <typename S>
-__device__ __forceinline__ void store_pop(S *dst, int64_t plane, int d, int i, int64_t k, double v, double ref) {
-    if constexpr (Codec<S>::shifted) v -= w_of(i) * ref;
-    dst[((int64_t)i * plane + k) * 2 + d] = Codec<S>::st((typename Codec<S>::C)v);
+// Element (in units of S) of component d of direction i of slot k.
+__device__ __forceinline__ int64_t pop_elem(int64_t ngroups, int d, int i, int64_t k) {
+    const int64_t half_pairs = ngroups * kHalfDirs * kGroup;
+    const int64_t pair = (i < kSplit ? 0 : half_pairs) + ((k / kGroup) * kHalfDirs + (i < kSplit ? i : i - kSplit)) * kGroup +
+                         k % kGroup;
+    return pair * 2 + d;
 }
 
 template <typename S>
-__device__ __forceinline__ double load_pop(const S *src, int64_t plane, int d, int i, int64_t k, double ref) {
-    double v = (double)Codec<S>::ld(src[((int64_t)i * plane + k) * 2 + d]);
+__device__ __forceinline__ void store_pop(S *dst, int64_t ngroups, int d, int i, int64_t k, double v, double ref) {
+    if constexpr (Codec<S>::shifted) v -= w_of(i) * ref;
+    dst[pop_elem(ngroups, d, i, k)] = Codec<S>::st((typename Codec<S>::C)v);
+}
+
+template <typename S>
+__device__ __forceinline__ double load_pop(const S *src, int64_t ngroups, int d, int i, int64_t k, double ref) {
+    double v = (double)Codec<S>::ld(src[pop_elem(ngroups, d, i, k)]);
     if constexpr (Codec<S>::shifted) v += w_of(i) * ref;
     return v;
 }
 
 // The set-up and exchange kernels address a fluid site s's populations by
-// its compact index idx[s] (solid sites have none).
+// its slot idx[s] (solid sites have none).
 template <typename S>
 __global__ void init_fields_kernel(S *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
-                                   const double *rho1, const double *u, int nx, int ny, int nz, int64_t plane,
+                                   const double *rho1, const double *u, int nx, int ny, int nz, int64_t ngroups,
                                    int eq_kind, double ref0, double ref1) {
     const int64_t N = (int64_t)nx * ny * nz;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
@@ -918,15 +1453,15 @@ __global__ void init_fields_kernel(S *dst, const uint32_t *links, const int32_t 
             const int64_t t = wall ? s : site_shift(x, y, z, cx_of(j), cy_of(j), cz_of(j), nx, ny, nz);
             const int kk = wall ? opp_of(j) : j;
             const double ux = u ? u[t] : 0.0, uy = u ? u[N + t] : 0.0, uz = u ? u[2 * N + t] : 0.0;
-            store_pop<S>(dst, plane, 0, j, k, feq_dir(kk, rho0[t], ux, uy, uz, eq_kind), ref0);
-            store_pop<S>(dst, plane, 1, j, k, feq_dir(kk, rho1[t], ux, uy, uz, eq_kind), ref1);
+            store_pop<S>(dst, ngroups, 0, j, k, feq_dir(kk, rho0[t], ux, uy, uz, eq_kind), ref0);
+            store_pop<S>(dst, ngroups, 1, j, k, feq_dir(kk, rho1[t], ux, uy, uz, eq_kind), ref1);
         });
     }
 }
 
 template <typename S>
 __global__ void set_pops_kernel(S *dst, const uint32_t *links, const int32_t *idx, const double *f, int nx, int ny,
-                                int nz, int64_t plane, double ref0, double ref1) {
+                                int nz, int64_t ngroups, double ref0, double ref1) {
     const int64_t N = (int64_t)nx * ny * nz;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t L = links[s];
@@ -941,14 +1476,14 @@ __global__ void set_pops_kernel(S *dst, const uint32_t *links, const int32_t *id
             const int kk = wall ? opp_of(j) : j;
 #pragma unroll
             for (int d = 0; d < 2; ++d)
-                store_pop<S>(dst, plane, d, j, k, f[(int64_t)(d * 19 + kk) * N + t], d == 0 ? ref0 : ref1);
+                store_pop<S>(dst, ngroups, d, j, k, f[(int64_t)(d * 19 + kk) * N + t], d == 0 ? ref0 : ref1);
         });
     }
 }
 
 template <typename S>
 __global__ void get_pops_kernel(const S *src, const uint32_t *links, const int32_t *idx, double *f, int nx, int ny,
-                                int nz, int64_t plane, double ref0, double ref1) {
+                                int nz, int64_t ngroups, double ref0, double ref1) {
     const int64_t N = (int64_t)nx * ny * nz;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t L = links[s];
@@ -967,7 +1502,7 @@ __global__ void get_pops_kernel(const S *src, const uint32_t *links, const int32
             const int kk = wall ? opp_of(i) : i;
             const int64_t k = idx[t];   // t is fluid here
 #pragma unroll
-            for (int d = 0; d < 2; ++d) f[(int64_t)(d * 19 + i) * N + s] = load_pop<S>(src, plane, d, kk, k, d == 0 ? ref0 : ref1);
+            for (int d = 0; d < 2; ++d) f[(int64_t)(d * 19 + i) * N + s] = load_pop<S>(src, ngroups, d, kk, k, d == 0 ? ref0 : ref1);
         });
     }
 }
@@ -988,7 +1523,7 @@ KArgs<S> make_kargs(const StepLaunch &L) {
     a.wpos = L.wpos;
     a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
     a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk;
-    a.plane_bytes = (uint32_t)(L.plane * 2 * (int64_t)sizeof(S));   // a plane of component pairs
+    a.half_bytes = (uint32_t)(L.ngroups * kHalfDirs * kGroup * 2 * (int64_t)sizeof(S));
     a.tau0 = (C)L.tau0; a.tau1 = (C)L.tau1; a.G = (C)L.G;
     a.gx = (C)L.gx; a.gy = (C)L.gy; a.gz = (C)L.gz;
     a.wall0 = (C)L.wall0; a.wall1 = (C)L.wall1; a.ref0 = (C)L.ref0; a.ref1 = (C)L.ref1;
@@ -1149,30 +1684,30 @@ hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, i
     }
 
 hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
-                              const double *rho1, const double *u, int nx, int ny, int nz, int64_t plane, int eq_kind,
+                              const double *rho1, const double *u, int nx, int ny, int nz, int64_t ngroups, int eq_kind,
                               const double ref[2], hipStream_t s) {
     const int g = site_grid((int64_t)nx * ny * nz);
     LBM_DISPATCH_PREC(prec, S,
                       hipLaunchKernelGGL(init_fields_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<S *>(dst), links,
-                                         idx, rho0, rho1, u, nx, ny, nz, plane, eq_kind, ref[0], ref[1]));
+                                         idx, rho0, rho1, u, nx, ny, nz, ngroups, eq_kind, ref[0], ref[1]));
     return hipGetLastError();
 }
 
 hipError_t launch_set_pops(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *f, int nx,
-                           int ny, int nz, int64_t plane, const double ref[2], hipStream_t s) {
+                           int ny, int nz, int64_t ngroups, const double ref[2], hipStream_t s) {
     const int g = site_grid((int64_t)nx * ny * nz);
     LBM_DISPATCH_PREC(prec, S,
                       hipLaunchKernelGGL(set_pops_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<S *>(dst), links,
-                                         idx, f, nx, ny, nz, plane, ref[0], ref[1]));
+                                         idx, f, nx, ny, nz, ngroups, ref[0], ref[1]));
     return hipGetLastError();
 }
 
 hipError_t launch_get_pops(int prec, const void *src, const uint32_t *links, const int32_t *idx, double *f, int nx,
-                           int ny, int nz, int64_t plane, const double ref[2], hipStream_t s) {
+                           int ny, int nz, int64_t ngroups, const double ref[2], hipStream_t s) {
     const int g = site_grid((int64_t)nx * ny * nz);
     LBM_DISPATCH_PREC(prec, S,
                       hipLaunchKernelGGL(get_pops_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<const S *>(src),
-                                         links, idx, f, nx, ny, nz, plane, ref[0], ref[1]));
+                                         links, idx, f, nx, ny, nz, ngroups, ref[0], ref[1]));
     return hipGetLastError();
 }
 
