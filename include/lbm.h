@@ -128,6 +128,18 @@ int lbm_moments(lbm_ctx *c, double *rho1, double *rho2, double *uF, int on_devic
  * sum rho2, sum rho u_F,x, sum rho u_F,y, sum rho u_F,z] (host array of 5). */
 int lbm_reduce(lbm_ctx *c, double out[5]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, allocation-free serving loops): the sums of lbm_reduce, written
+ * to out_dev, a device array of 5 doubles, on the context's stream without
+ * synchronizing.  It allocates nothing: the per-block partial sums go to a
+ * fixed work array of the library on each GPU (at most 16384 blocks, 1 MiB,
+ * held until the process ends) instead of the context's own.  All calls on
+ * one GPU share that array, so calls that overlap in time on one GPU (on
+ * different streams or host threads) race; calls ordered on one stream do
+ * not.  Errors: LBM_EINVAL (NULL argument, or a context whose step runs more
+ * than 16384 blocks), LBM_EDEVICE. */
+int lbm_reduce_noalloc(lbm_ctx *c, double *out_dev);
+
 /* Checkpoint: copies the current populations f_i(x, t) (2*19*N doubles, the
  * ABI layout above) out; solid sites give 0. */
 int lbm_get_populations(lbm_ctx *c, double *f, int on_device);

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -60,6 +61,36 @@ struct lbm_batch {
 };
 
 namespace {
+
+// Work memory of lbm_reduce_noalloc: the per-block partial sums of one
+// reduction (kPartialStride doubles per block, at most kScratchBlocks
+// blocks) followed by their total.  One copy per GPU, held until the process
+// ends; host code reaches it only through the address that
+// hipGetSymbolAddress gives for the current device (scratch_ptr).
+constexpr int kScratchBlocks = 16384;
+constexpr size_t kScratchDoubles = (size_t)(kScratchBlocks + 1) * lbm::kPartialStride;
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_ptr;   // device address of scratch, per device (nullptr: not looked up yet)
+
+// Looks up the device address of scratch on the current device, once per
+// device.  Returns hipSuccess and leaves it in g_scratch_ptr[dev].
+hipError_t scratch_setup(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    double *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+    return hipSuccess;
+}
+
+double *scratch_ptr(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return dev < (int)g_scratch_ptr.size() ? g_scratch_ptr[dev] : nullptr;
+}
 
 // Plain steps per captured graph (even, so a replay returns to the buffer it
 // started from).
@@ -419,6 +450,11 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         return rc;
     };
     if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(c, LBM_EDEVICE, "no HIP device"));
+    {   // the allocation-free reduction's work memory on this device
+        const hipError_t e = scratch_setup(c->device);
+        if (e != hipSuccess)
+            return bail(fail(c, LBM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)));
+    }
     if (p.stream) c->stream = static_cast<hipStream_t>(p.stream);
     else {
         if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
@@ -631,6 +667,29 @@ int lbm_reduce(lbm_ctx *c, double out[5]) {
     int rc = measure(c, nullptr, nullptr, nullptr);
     if (rc) return rc;
     for (int k = 0; k < 5; ++k) out[k] = c->red_host[k];
+    return LBM_OK;
+}
+
+int lbm_reduce_noalloc(lbm_ctx *c, double *out_dev) {
+    if (!c || !out_dev) return fail(c, LBM_EINVAL, "lbm_reduce_noalloc: NULL argument");
+    const int nb = nblocks(c);
+    if (nb > kScratchBlocks) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "lbm_reduce_noalloc: the step runs %d blocks, more than the %d its work memory holds",
+                      nb, kScratchBlocks);
+        return fail(c, LBM_EINVAL, buf);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    double *ws = scratch_ptr(c->device);
+    if (!ws) return fail(c, LBM_EDEVICE, "lbm_reduce_noalloc: work memory of this device not set up");
+    double *total = ws + (size_t)kScratchBlocks * lbm::kPartialStride;
+    // Every block writes its own partial sums and the total is overwritten
+    // whole, so nothing needs clearing between calls.
+    lbm::StepLaunch L = make_launch(c, c->f[c->cur], nullptr);
+    L.partials = ws;
+    HIPCHK(c, lbm::launch_step(c->p.prec, lbm::MODE_MOMENTS, L, c->stream));
+    HIPCHK(c, lbm::launch_finalize(ws, nb, total, c->stream));
+    HIPCHK(c, hipMemcpyAsync(out_dev, total, sizeof(double) * 5, hipMemcpyDeviceToDevice, c->stream));
     return LBM_OK;
 }
 

@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16s": LBM_FP16S, "bf16s": L
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_EMASSDRIFT = 0, -1, -2, -3, -4, -5
 ERROR_NAMES = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_ENONFINITE", -5: "LBM_EMASSDRIFT"}
 
-EXPORTED = ("lbm_init", "lbm_step", "lbm_moments", "lbm_reduce", "lbm_get_populations",
+EXPORTED = ("lbm_init", "lbm_step", "lbm_moments", "lbm_reduce", "lbm_reduce_noalloc", "lbm_get_populations",
             "lbm_set_populations", "lbm_set_fields", "lbm_info", "lbm_last_error", "lbm_free",
             "lbm_batch_create", "lbm_batch_step", "lbm_batch_last_error", "lbm_batch_free")
 
@@ -89,6 +89,7 @@ def load_library():
     lib.lbm_step.argtypes = [vp, ctypes.c_int64]
     lib.lbm_moments.argtypes = [vp, vp, vp, vp, ctypes.c_int]
     lib.lbm_reduce.argtypes = [vp, dp]
+    lib.lbm_reduce_noalloc.argtypes = [vp, vp]
     lib.lbm_get_populations.argtypes = [vp, vp, ctypes.c_int]
     lib.lbm_set_populations.argtypes = [vp, vp, ctypes.c_int]
     lib.lbm_set_fields.argtypes = [vp, vp, vp, vp, ctypes.c_int]
@@ -250,6 +251,16 @@ def lbm_moments(ctx: Context, rho1=None, rho2=None, uF=None):
 def lbm_reduce(ctx: Context) -> np.ndarray:
     out = np.zeros(5)
     _check(ctx, load_library().lbm_reduce(ctx.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def lbm_reduce_noalloc(ctx: Context, out):
+    """The sums of lbm_reduce into out, a float64 torch tensor of 5 on the
+    GPU, enqueued on the context's stream (not synchronized)."""
+    p, d = _ptr(out)
+    if not d or out.numel() < 5:
+        raise LBMError(LBM_EINVAL, "lbm_reduce_noalloc writes a device array of 5 doubles")
+    _check(ctx, load_library().lbm_reduce_noalloc(ctx.handle, p))
     return out
 
 
