@@ -507,9 +507,10 @@ int ora_reduce(const ora_params *p, const double *f, double out[5])
 
 /* ------------------------------------------------------------------------- */
 /* One step evaluated at chosen sites only, for spot checks on lattices too  */
-/* large to step whole.  Same equations, applied to the few sites that the   */
-/* requested outputs depend on: f(x, t+1) needs f* at x and at x - c_i, and   */
-/* each of those needs rho at its own neighbours.                            */
+/* large to step whole.  Same equations, in the same order, applied to the   */
+/* few sites that the requested outputs depend on: f(x, t+1) needs f* at x   */
+/* and at x - c_i, and each of those needs rho at its own neighbours.  Its   */
+/* results equal ora_step's bit for bit (pinned by the CPU tests).           */
 /* ------------------------------------------------------------------------- */
 
 static void site_moments(const ora_params *p, const double *f, int64_t s, double rho[2], double j[2][3])
@@ -533,29 +534,61 @@ static double site_density(const ora_params *p, const double *f, int64_t s, int 
     return r;
 }
 
-/* Post-collision populations of the fluid site s (Eqs. 3-11). */
+/* Eqs. (7) and (11) with the body force, at the fluid site s: the same sums
+ * in the same order as field_force(), with the neighbours' densities summed
+ * on the spot (the fluid-fluid part and the wall part of each component's
+ * force apart, then the wall kind's combination). */
+static void site_force(const ora_params *p, const double *f, int64_t s, const double rho[2], double F[2][3])
+{
+    double ff[2][3] = {{0, 0, 0}, {0, 0, 0}}, fw[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    for (int a = 0; a < 2; ++a) {
+        int b = 1 - a;
+        for (int i = 0; i < Q; ++i) {
+            int64_t n = shifted(p, s, CV[i][0], CV[i][1], CV[i][2]);
+            int wall = is_solid(p, n);
+            double rho_b = wall ? 0.0 : site_density(p, f, n, b);
+            for (int d = 0; d < 3; ++d) {
+                if (wall)
+                    fw[a][d] += weight(i) * CV[i][d] * wall_density(p->rho_s, b);
+                else
+                    ff[a][d] += weight(i) * CV[i][d] * rho_b;
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            ff[a][d] *= p->G * rho[a];
+            fw[a][d] *= p->G * rho[a];
+        }
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int d = 0; d < 3; ++d) {
+            double wall = fw[a][d];
+            if (p->wall_kind == 1) {
+                double rho_mix = rho[0] + rho[1];
+                wall -= rho[a] / rho_mix * (fw[0][d] + fw[1][d]);
+            }
+            F[a][d] = ff[a][d] + wall + rho[a] * p->g[d];
+        }
+}
+
+/* Post-collision populations of the fluid site s (Eqs. 3-11), computed as
+ * field_moments() ... field_collide() compute them for that site. */
 static void site_collide(const ora_params *p, const double *f, int64_t s, double fstar[2][Q])
 {
     int64_t N = nsites(p);
     double rho[2], j[2][3], F[2][3];
     site_moments(p, f, s, rho, j);
-    for (int a = 0; a < 2; ++a) {
-        int b = 1 - a;
-        double acc[3] = {0.0, 0.0, 0.0};
-        for (int i = 0; i < Q; ++i) {
-            int64_t n = shifted(p, s, CV[i][0], CV[i][1], CV[i][2]);
-            double rho_prime = is_solid(p, n) ? wall_density(p->rho_s, b) : site_density(p, f, n, b);
-            for (int d = 0; d < 3; ++d) acc[d] += weight(i) * CV[i][d] * rho_prime;
-        }
-        for (int d = 0; d < 3; ++d) F[a][d] = p->G * rho[a] * acc[d] + rho[a] * p->g[d];
-    }
+    site_force(p, f, s, rho, F);
     double rho_mix = rho[0] + rho[1];
     double u[3];
-    for (int d = 0; d < 3; ++d)
-        u[d] = (j[0][d] + j[1][d]) / rho_mix + ((F[0][d] + F[1][d]) / rho_mix) / 2.0;
+    for (int d = 0; d < 3; ++d) {
+        double bare = (j[0][d] + j[1][d]) / rho_mix;
+        double g = (F[0][d] + F[1][d]) / rho_mix;
+        u[d] = bare + g / 2.0;
+    }
     double nu1 = T0 * (p->tau[0] - 0.5), nu2 = T0 * (p->tau[1] - 0.5);
-    double frac = rho[0] / rho_mix;
-    double tau_mix = (frac * nu1 + (1.0 - frac) * nu2) / T0 + 0.5;
+    double frac = rho[0] / (rho[0] + rho[1]);
+    double nu_mix = frac * nu1 + (1.0 - frac) * nu2;
+    double tau_mix = nu_mix / T0 + 0.5;
     for (int a = 0; a < 2; ++a) {
         double fs[Q], feq[Q], fprime[Q], Pi[9], forcing[Q];
         for (int i = 0; i < Q; ++i) fs[i] = f[(a * Q + i) * N + s];

@@ -126,21 +126,52 @@ def _sharp_profile(A, B, nuA, nuB, g):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("nuA,nuB", [(1 / 60, 1 / 60), (1 / 60, 1 / 6), (1 / 6, 1 / 60), (1 / 60, 1 / 600)])
+@pytest.mark.parametrize("nuA,nuB", [(1 / 60, 1 / 60), (1 / 60, 1 / 6), (1 / 6, 1 / 60), (1 / 60, 1 / 600),
+                                     (0.0017, 0.17), (0.0017, 1.7), (1.7, 0.0017)])
 def test_two_layer_poiseuille(one_thread, nuA, nuB):
-    """Section 3.2: layered flow at viscosity ratios 1, 10, 0.1 and 10 with
-    a kinematic viscosity down to 1/600 (tau = 0.505), against the analytic
-    solution with the density-weighted viscosity: within 2.5 % of u_max with
-    the measured density profile, within 8 % with sharp layers (the
-    interface is about 4 sites wide in a 30-site channel)."""
+    """Section 3.2: layered flow at viscosity ratios 1, 10, 0.1, 10 (with a
+    kinematic viscosity of 1/600, tau = 0.505), 100, 1000 and 1/1000 (with the
+    lowest viscosity 0.0017, tau = 0.5051), against the analytic solution of
+    the layered momentum balance d/dy (mu du/dy) = -rho g with the
+    density-weighted viscosity of Eq. (6) integrated over the measured
+    density profile: within 2.5 % of u_max (measured at most 1.6 %).  The
+    sharp-layer closed form (uniform layers) is asserted up to ratio 10
+    (within 8 %): at ratios of 100 and more the few per cent of the other
+    component in each layer, and the film of it at the neutral walls, set
+    the low-viscosity layer's mixture viscosity, which uniform layers ignore
+    (16-54 % off; the quadrature still agrees)."""
     ora = one_thread
     g = 1e-6
     A, B, uz = _two_layer(ora, 30, nuA, nuB, G=-3.0, force_kind=0, g=g)
     quad = _quadrature_profile(A, B, nuA, nuB, g)
-    sharp = _sharp_profile(A, B, nuA, nuB, g)
     umax = np.abs(uz).max()
     assert np.abs(uz - quad).max() <= 0.025 * umax
-    assert np.abs(uz - sharp).max() <= 0.08 * umax
+    if max(nuA, nuB) / min(nuA, nuB) <= 10.0001:
+        sharp = _sharp_profile(A, B, nuA, nuB, g)
+        assert np.abs(uz - sharp).max() <= 0.08 * umax
+
+
+@pytest.mark.slow
+def test_two_layer_channel_ratio_1000(one_thread):
+    """The layered channel of the workloads across its width (62 fluid rows
+    between walls, the 1 x 64 x 1 column equivalent to 8 x 64 x 256), G = -4.2
+    with minority densities near their coexistence value, viscosities 0.0017
+    and 1.7 (ratio 1000, tau = 0.5051 and 5.6): the steady profile against
+    the density-weighted quadrature of Section 3.2 within 1 % of u_max
+    (measured 0.73 %)."""
+    ora = one_thread
+    g = 1e-6
+    ny = 64
+    solid = _channel(ny)
+    r1, r2 = inputs.two_layer((1, ny, 1), 1.0, 0.005)
+    r1[solid == 1] = 0
+    r2[solid == 1] = 0
+    p = ora.Params(1, ny, 1, tau=(0.0017 / T0 + 0.5, 1.7 / T0 + 0.5), G=-4.2, g=(0, 0, g), solid=solid)
+    f, _ = _run_to_steady(ora, p, ora.init(p, r1, r2), 20000, 600000, 5e-9)
+    a, b, u = ora.moments(p, f)
+    A, B, uz = a[0, 1:-1, 0], b[0, 1:-1, 0], u[2, 0, 1:-1, 0]
+    quad = _quadrature_profile(A, B, 0.0017, 1.7, g)
+    assert np.abs(uz - quad).max() <= 0.01 * np.abs(uz).max()
 
 
 def test_first_order_forcing_misses_layered_profile(one_thread):
