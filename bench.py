@@ -110,36 +110,55 @@ def time_precision(lbm, torch, prec, solid, rA, rB, phys, steps, warmup, check_e
 
 
 def cpu_baseline(solid, rA, rB, phys, steps=3):
-    """The FP64 oracle on the same lattice, timed on the host's cores."""
+    """The FP64 oracle on the same lattice, timed on the host: on the threads
+    the job is given (OMP_NUM_THREADS; the box allots 16 host threads per GPU)
+    for `steps` steps, and on one thread for one step."""
     from oracle import oracle as ora
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    threads = min(threads, 16)
-    ora.set_threads(threads)
     n = solid.shape[0]
     p = ora.Params(n, n, n, solid=solid, **phys)
     f = ora.init(p, rA, rB)
-    t0 = time.perf_counter()
-    ora.run(p, f, steps)
-    dt = time.perf_counter() - t0
     nf = int((solid == 0).sum())
-    return {"value": nf * steps / dt / 1e6, "unit": "MLUPS", "cores": ora.get_threads(), "kind": "oracle",
-            "sample": f"the full {n}^3 workload, {steps} steps of the FP64 oracle ({dt:.1f} s)"}
+    out = {}
+    for nthr, k in ((threads, steps), (1, 1)):
+        ora.set_threads(nthr)
+        t0 = time.perf_counter()
+        ora.run(p, f, k)
+        dt = time.perf_counter() - t0
+        out[nthr] = (nf * k / dt / 1e6, ora.get_threads(), k, dt)
+    ora.set_threads(threads)
+    v, used, k, dt = out[threads]
+    v1, _, k1, dt1 = out[1]
+    return {"value": v, "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "sample": f"the full {n}^3 workload, {k} steps of the FP64 oracle on {used} threads ({dt:.1f} s)",
+            "one_thread": {"value": v1, "unit": "MLUPS", "cores": 1,
+                           "sample": f"the full {n}^3 workload, {k1} step on one thread ({dt1:.1f} s)"},
+            "host_cpus": os.cpu_count()}
 
 
-def ensemble(lbm, torch, steps, warmup):
+TUNED = os.path.join(ROOT, "paper_1711_03254_amd", "tuned", "launch_shapes.json")
+
+
+def ensemble(lbm, torch, steps, warmup, tune=False):
     """The batched ensemble: 64 ducts of uneven sizes stepped by one
     graph-replayed launch per step, against the same domains stepped one
     launch each.  FP32; MLUPS over all fluid sites; wall clock with the
-    device synchronized on both sides (the batch runs on its own stream)."""
-    from paper_1711_03254_amd import inputs
+    device synchronized on both sides (the batch runs on its own stream).
+    The launch shape is the autotuner's, from its committed cache (tune=True
+    tunes first and rewrites the cache)."""
+    from paper_1711_03254_amd import autotune, inputs
     doms = inputs.ensemble_case(64)
+    if tune:
+        autotune.tune_batch(doms, "fp32", cache=TUNED)
+    shape = autotune.cached_batch_shape(doms, "fp32", TUNED)
+    tile, zc = (tuple(shape["tile"]), shape["zchunk"]) if shape else ((64, 8), 0)
     stream = torch.cuda.Stream()
     ctxs = []
     for d in doms:
         nz, ny, nx = d["shape"]
         ctxs.append(lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.LBM_FP32, solid=d["solid"],
                                             rho_init=(d["rho_A"], d["rho_B"]), tau=d["tau"], G=d["G"], g=d["g"],
-                                            rho_s=d["rho_s"], stream=stream, tile=(64, 8))))
+                                            rho_s=d["rho_s"], stream=stream, tile=tile, zchunk=zc)))
     nf = sum(lbm.lbm_info(c)["n_fluid"] for c in ctxs)
     for c in ctxs:
         lbm.lbm_step(c, warmup)
@@ -159,7 +178,8 @@ def ensemble(lbm, torch, steps, warmup):
     lbm.lbm_batch_free(b)
     for c in ctxs:
         lbm.lbm_free(c)
-    out = {"domains": len(doms), "n_fluid": nf, "steps": steps}
+    out = {"domains": len(doms), "n_fluid": nf, "steps": steps,
+           "launch": {"tile": list(tile), "zchunk": zc, "tuned": shape is not None}}
     for name, t in (("batched", t_batch), ("one_launch_per_domain", t_single)):
         mlups = nf * steps / t / 1e6
         out[name] = {"ms_per_step": round(t / steps * 1e3, 4), "mlups": round(mlups, 1),
@@ -222,6 +242,8 @@ def main():
                     help="skip the cold / warm time-to-steady-state comparison")
     ap.add_argument("--no-all-fluid", dest="all_fluid", action="store_false",
                     help="skip the all-fluid lattice of the same size")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the ensemble's launch shape and rewrite the committed cache")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -269,7 +291,7 @@ def main():
             print(f"# all-fluid {prec}: {json.dumps(allf[prec])}", file=sys.stderr, flush=True)
     ens = None
     if args.ensemble:
-        ens = ensemble(lbm, torch, max(20, args.steps // 5), 4)
+        ens = ensemble(lbm, torch, max(20, args.steps // 5), 4, tune=args.tune)
         print(f"# ensemble: {json.dumps(ens)}", file=sys.stderr, flush=True)
     ws_res = None
     if args.warm_start:

@@ -97,6 +97,12 @@ typedef struct {
                                     net wall force, so that the walls separate the components
                                     without pushing the mixture (W2, the momentum-balanced wall
                                     interaction of Section 3.3) */
+    double tau_crit;             /* FP32 and 16-bit storage: sites whose mixture relaxation time
+                                    (Eqs. 5-6) is below tau_crit accumulate the second moments of
+                                    the collision (the non-equilibrium flux of Eq. 10) in FP64:
+                                    near tau = 1/2 (low viscosity) that flux is a small difference
+                                    of sums of size rho / 3.  0 = never (default); FP64 storage
+                                    computes everything in FP64 and ignores it */
 } lbm_params;
 
 /* Creates a context: validates p, allocates the device state and sets the
@@ -146,7 +152,11 @@ int lbm_get_populations(lbm_ctx *c, double *f, int on_device);
 
 /* Resume / test hook: replaces the state by the populations f (2*19*N
  * doubles, the ABI layout; solid sites ignored), rounded to the storage
- * precision.  get after set returns f exactly at FP64. */
+ * precision.  get after set returns f exactly at FP64.  The component masses
+ * of the periodic check are re-recorded from the new state, and at 16 bits a
+ * default shift reference (rho_ref 0) is recomputed as the new state's mean
+ * density, so a checkpoint resumes correctly into a context created from
+ * placeholder fields. */
 int lbm_set_populations(lbm_ctx *c, const double *f, int on_device);
 
 /* Warm start: replaces the state by f_eq(rho1, rho2, u) as lbm_init does.

@@ -5,12 +5,14 @@ few z-chunk depths through the C ABI (HIP events on a dedicated stream, after
 warm-up steps) and keeps the fastest; results are cached in a JSON file keyed
 by precision and domain shape, so a run pays for tuning once.
 
-A batch shares one tile shape (one kernel instance per launch) but each domain
-keeps its own z-chunk, so `tune_batch` picks the tile that minimizes the
-summed step time of the domains, each at its best z-chunk.
+A batch shares one tile shape (one kernel instance per launch); `tune_batch`
+times the whole batch at each candidate tile and z-chunk and keeps the
+fastest.  The cache of the benchmark's ensemble is committed with the package
+(tuned/launch_shapes.json); bench.py reads it.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 
@@ -76,34 +78,75 @@ def tune_domain(dom: dict, prec: str = "fp32", steps: int = 20, warmup: int = 4,
     return res
 
 
-def tune_batch(domains: list, prec: str = "fp32", steps: int = 10, warmup: int = 2, cache: str | None = None,
-               tiles=TILES, zchunks=ZCHUNKS) -> dict:
-    """One tile for the whole batch (the one minimizing the summed step time
-    of the distinct domain shapes) and a z-chunk per domain."""
-    per_shape = {}
+def batch_key(domains: list, prec: str) -> str:
+    """Cache key of a set of domains: precision, count, and a digest of their
+    shapes and solid masks."""
+    h = hashlib.sha256(prec.encode())
     for d in domains:
-        k = tuple(d["shape"])
-        if k not in per_shape:
-            per_shape[k] = (d, tune_domain(d, prec, steps, warmup, cache, tiles, zchunks))
-    best_tile, best_total = None, None
-    for tile in tiles:
-        tname = f"{tile[0]}x{tile[1]}"
-        total = 0.0
+        h.update(repr(tuple(d["shape"])).encode())
+        h.update(np.ascontiguousarray(d["solid"], dtype=np.uint8).tobytes())
+    return f"batch:{prec}:{len(domains)}:{h.hexdigest()[:16]}"
+
+
+def _time_batch(lbm, prec, domains, tile, zchunk, steps, warmup):
+    """Seconds per batched step of the domains at one tile shape (None if the
+    tile is not compiled for this precision or does not fit a domain)."""
+    import time
+
+    import torch
+    ctxs = []
+    try:
         for d in domains:
-            allt = per_shape[tuple(d["shape"])][1]["all"]
-            cand = [v for k, v in allt.items() if k.startswith(tname + "/")]
-            if not cand:
-                total = None
-                break
-            total += min(cand)
-        if total is not None and (best_total is None or total < best_total):
-            best_tile, best_total = tile, total
-    zc = []
-    for d in domains:
-        allt = per_shape[tuple(d["shape"])][1]["all"]
-        tname = f"{best_tile[0]}x{best_tile[1]}/"
-        zc.append(int(min((k for k in allt if k.startswith(tname)), key=allt.get).split("/")[1]))
-    return {"tile": list(best_tile), "zchunk": zc, "sum_ms": best_total}
+            nz, ny, nx = d["shape"]
+            ctxs.append(lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=d["solid"],
+                                                rho_init=(d["rho_A"], d["rho_B"]), tau=d["tau"], G=d["G"], g=d["g"],
+                                                rho_s=d["rho_s"], tile=tile, zchunk=zchunk)))
+    except lbm.LBMError as e:
+        if e.code == lbm.LBM_EINVAL:
+            return None
+        raise
+    b = lbm.lbm_batch_create(ctxs)
+    lbm.lbm_batch_step(b, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lbm.lbm_batch_step(b, steps)   # returns when the work is done
+    dt = (time.perf_counter() - t0) / steps
+    lbm.lbm_batch_free(b)
+    for c in ctxs:
+        lbm.lbm_free(c)
+    return dt
+
+
+def tune_batch(domains: list, prec: str = "fp32", steps: int = 16, warmup: int = 4, cache: str | None = None,
+               tiles=((64, 8), (64, 16), (32, 16), (32, 8)), zchunks=(0, 32)) -> dict:
+    """The launch shape of a batch: every (tile, z-chunk) candidate is timed
+    on the whole batch (one launch per step over all domains' tiles, as
+    lbm_batch_step runs it) and the fastest kept; z-chunk 0 is each
+    context's default.  Cached under batch_key(domains, prec)."""
+    from . import lbm
+    lbm.load_library()
+    key = batch_key(domains, prec)
+    table = _load(cache)
+    if key in table:
+        return table[key]
+    times = {}
+    for tile in tiles:
+        for zc in zchunks:
+            t = _time_batch(lbm, prec, domains, tile, zc, steps, warmup)
+            if t is not None:
+                times[f"{tile[0]}x{tile[1]}/{zc}"] = t * 1e3
+    best = min(times, key=times.get)
+    tile, zc = best.split("/")
+    res = {"tile": [int(v) for v in tile.split("x")], "zchunk": int(zc), "ms": times[best], "all_ms": times,
+           "domains": len(domains), "prec": prec}
+    table[key] = res
+    _save(cache, table)
+    return res
+
+
+def cached_batch_shape(domains: list, prec: str, cache: str):
+    """The cached launch shape of this batch, or None if it was never tuned."""
+    return _load(cache).get(batch_key(domains, prec))
 
 
 def _load(path):

@@ -47,6 +47,7 @@ struct lbm_ctx {
 struct lbm_batch {
     std::vector<lbm_ctx *> ctx;
     int prec = 0, tile_x = 0, tile_y = 0;
+    bool hi = false;                // some domain forms the flux in FP64 below its tau_crit
     hipStream_t stream = nullptr;
     size_t desc_size = 0;
     std::vector<char> descs_host;
@@ -194,6 +195,7 @@ lbm::StepLaunch make_launch(const lbm_ctx *c, const void *src, void *dst) {
     L.wall1 = p.rho_s > 0 ? p.rho_s : 0.0;    // rho^s_2 =  rho^s Theta(rho^s)
     L.ref0 = c->ref[0];
     L.ref1 = c->ref[1];
+    L.tau_crit = p.tau_crit;
     L.eq_kind = p.eq_kind; L.force_kind = p.force_kind; L.wall_kind = p.wall_kind;
     L.partials = c->partials;
     return L;
@@ -417,6 +419,8 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
     if (p.check_every < 0) return fail(nullptr, LBM_EINVAL, "check_every must be >= 0");
     if (!(p.mass_tol >= 0) || !std::isfinite(p.rho_ref[0]) || !std::isfinite(p.rho_ref[1]))
         return fail(nullptr, LBM_EINVAL, "mass_tol must be >= 0 and rho_ref finite");
+    if (!(p.tau_crit >= 0) || !std::isfinite(p.tau_crit))
+        return fail(nullptr, LBM_EINVAL, "tau_crit must be finite and >= 0");
     if (!p.rho_init[0] || !p.rho_init[1]) return fail(nullptr, LBM_EINVAL, "rho_init pointers are NULL");
     if ((p.tile_x || p.tile_y) && !lbm::tile_supported(p.tile_x, p.tile_y))
         return fail(nullptr, LBM_EINVAL, "unsupported tile (64x4, 32x8, 16x16, 8x32, 64x8, 32x16 or 64x16)");
@@ -563,6 +567,16 @@ int evaluate_check(lbm_ctx *c) {
 int64_t plain_steps_before_check(int64_t done, int every) {
     if (every <= 0) return INT64_MAX;
     return every - 1 - done % every;
+}
+
+// Discards the captured step graphs (they are captured again on next use).
+void drop_ctx_graphs(lbm_ctx *c) {
+    for (int k = 0; k < 2; ++k) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+        c->gexec[k] = nullptr;
+        c->graph[k] = nullptr;
+    }
 }
 
 // Captures kGraphSteps plain steps starting from buffer `parity`.
@@ -726,11 +740,40 @@ int lbm_set_populations(lbm_ctx *c, const double *f, int on_device) {
             return fail(c, LBM_EDEVICE, "set_populations: copy failed");
         }
     }
-    hipError_t e = lbm::launch_set_pops(c->p.prec, c->f[c->cur], c->links, c->idx, src, c->p.nx, c->p.ny, c->p.nz, c->ngroups,
-                                        c->ref, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    auto encode = [&]() {
+        hipError_t e = lbm::launch_set_pops(c->p.prec, c->f[c->cur], c->links, c->idx, src, c->p.nx, c->p.ny, c->p.nz,
+                                            c->ngroups, c->ref, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        return e;
+    };
+    hipError_t e = encode();
+    int rc = LBM_OK;
+    const bool shifted = c->p.prec == LBM_FP16S || c->p.prec == LBM_BF16S;
+    if (e == hipSuccess && shifted && (c->p.rho_ref[0] == 0 || c->p.rho_ref[1] == 0)) {
+        // A default shift reference is the mean density of the state the
+        // context holds: recompute it for the resumed state (the context may
+        // have been created from placeholder fields) and encode again.
+        rc = measure(c, nullptr, nullptr, nullptr);
+        if (rc == LBM_OK) {
+            double ref[2] = {c->ref[0], c->ref[1]};
+            for (int a = 0; a < 2; ++a)
+                if (c->p.rho_ref[a] == 0) ref[a] = c->red_host[a] / (double)c->nfluid;
+            if (ref[0] != c->ref[0] || ref[1] != c->ref[1]) {
+                c->ref[0] = ref[0];
+                c->ref[1] = ref[1];
+                drop_ctx_graphs(c);   // the captured steps carry the old reference
+                e = encode();
+            }
+        }
+    }
     if (!on_device) (void)hipFree(src);
     if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("set_populations: ") + hipGetErrorString(e));
+    if (rc) return rc;
+    // The periodic check compares against the masses of the resumed state.
+    rc = measure(c, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    c->mass0[0] = c->red_host[0];
+    c->mass0[1] = c->red_host[1];
     return LBM_OK;
 }
 
@@ -781,6 +824,7 @@ int lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, lbm_batch **out) {
     b->prec = ctxs[0]->p.prec;
     b->tile_x = ctxs[0]->tile_x;
     b->tile_y = ctxs[0]->tile_y;
+    for (int d = 0; d < n; ++d) b->hi = b->hi || ctxs[d]->p.tau_crit > 0;
     b->desc_size = lbm::batch_desc_size(b->prec);
     b->descs_host.resize(b->desc_size * n);
     // Z-chunks of the batch.  A context's own z-chunk fills the GPU with
@@ -864,7 +908,7 @@ bool capture_batch_graph(lbm_batch *b) {
     }
     hipError_t e = hipSuccess;
     for (int j = 0; j < kGraphSteps && e == hipSuccess; ++j)
-        e = lbm::launch_batch(b->prec, lbm::MODE_STEP, b->tile_x, b->tile_y, b->descs_dev, b->work_dev, b->nwork,
+        e = lbm::launch_batch(b->prec, lbm::MODE_STEP, b->hi, b->tile_x, b->tile_y, b->descs_dev, b->work_dev, b->nwork,
                               j & 1, b->stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);
@@ -904,7 +948,7 @@ int lbm_batch_step(lbm_batch *b, int64_t n) {
         for (lbm_ctx *c : b->ctx) plain = std::min(plain, plain_steps_before_check(c->steps_done, c->p.check_every));
         if (plain >= kGraphSteps + flip) {
             if (flip) {  // align to an even step before replaying
-                if (lbm::launch_batch(b->prec, lbm::MODE_STEP, b->tile_x, b->tile_y, b->descs_dev, b->work_dev,
+                if (lbm::launch_batch(b->prec, lbm::MODE_STEP, b->hi, b->tile_x, b->tile_y, b->descs_dev, b->work_dev,
                                       b->nwork, 1, b->stream) != hipSuccess)
                     return bfail(b, LBM_EDEVICE, "batch launch failed");
                 advance(1);
@@ -920,14 +964,14 @@ int lbm_batch_step(lbm_batch *b, int64_t n) {
             }
         }
         for (; plain > 0; --plain, ++k) {
-            if (lbm::launch_batch(b->prec, lbm::MODE_STEP, b->tile_x, b->tile_y, b->descs_dev, b->work_dev, b->nwork,
+            if (lbm::launch_batch(b->prec, lbm::MODE_STEP, b->hi, b->tile_x, b->tile_y, b->descs_dev, b->work_dev, b->nwork,
                                   flip, b->stream) != hipSuccess)
                 return bfail(b, LBM_EDEVICE, "batch launch failed");
             advance(1);
             flip ^= 1;
         }
         if (k < n) {  // a check step for at least one domain
-            if (lbm::launch_batch(b->prec, lbm::MODE_CHECK, b->tile_x, b->tile_y, b->descs_dev, b->work_dev, b->nwork,
+            if (lbm::launch_batch(b->prec, lbm::MODE_CHECK, b->hi, b->tile_x, b->tile_y, b->descs_dev, b->work_dev, b->nwork,
                                   flip, b->stream) != hipSuccess)
                 return bfail(b, LBM_EDEVICE, "batch launch failed");
             std::vector<lbm_ctx *> due;

@@ -48,6 +48,7 @@ struct StepLaunch {
     int tile_x, tile_y, zchunk;
     int ntx, nty, nzc;      // tiles in x, y and chunks in z
     double tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
+    double tau_crit;        // 32/16-bit storage: sites with tau_mix below it form P_ab in FP64
     int eq_kind, force_kind, wall_kind;
     double *partials;       // kPartialStride doubles per block
     double *out_rho0, *out_rho1, *out_u;  // MODE_MOMENTS outputs (N, N, 3N)
@@ -76,7 +77,8 @@ hipError_t launch_get_pops(int prec, const void *src, const uint32_t *links, con
 // of (domain, tile) pairs; flip swaps each descriptor's (src, dst).
 size_t batch_desc_size(int prec);
 void fill_batch_desc(int prec, const StepLaunch &L, void *out);
-hipError_t launch_batch(int prec, Mode mode, int tx, int ty, const void *descs, const int2 *work, int nwork,
+// hi: some domain uses the FP64 flux below tau_crit (the HI instances).
+hipError_t launch_batch(int prec, Mode mode, bool hi, int tx, int ty, const void *descs, const int2 *work, int nwork,
                         int flip, hipStream_t s);
 
 // Tile shapes the step kernel is compiled for.

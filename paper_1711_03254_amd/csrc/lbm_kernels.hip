@@ -118,6 +118,7 @@ struct KArgs {
     int nx, ny, nz, ntx, nty, zchunk;
     uint32_t half_bytes;    // bytes of one buffer half (directions 0-10 or 11-18)
     C tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
+    C tau_crit;             // sites with tau_mix below it form P_ab in FP64 (32/16-bit storage)
     int eq_kind, force_kind, wall_kind;
     double *partials;
     double *out_rho0, *out_rho1, *out_u;
@@ -210,11 +211,24 @@ __device__ __forceinline__ void pair_store(S a, S b, __amdgpu_buffer_rsrc_t r, u
 }
 
 // Eq. (4) and the second moments of one component's pulled populations:
-// everything the regularized collision needs from them.
+// everything the regularized collision needs from them.  xx .. yz hold the
+// second moments relative to the equilibrium of Eq. (3) at rest,
+// P_ab = sum_i c_ia c_ib f_i - rho T0 delta_ab: the non-equilibrium flux that
+// Eq. (10) projects, plus the equilibrium's own velocity terms (none for the
+// printed Eq. 3).
 template <typename C>
 struct Moments {
     C r, jx, jy, jz, xx, yy, zz, xy, xz, yz;
 };
+
+// Second moments -> P_ab (the diagonal loses rho T0).
+template <typename C>
+__device__ __forceinline__ void to_flux(Moments<C> &m) {
+    const C rt = m.r * C(1.0 / 3.0);
+    m.xx = m.xx - rt;
+    m.yy = m.yy - rt;
+    m.zz = m.zz - rt;
+}
 
 // Adds s * v to an accumulator for a compile-time sign s in {-1, 0, 1}.
 // Accumulators start at -0, which the compiler drops from the first sum.
@@ -259,6 +273,7 @@ __device__ __forceinline__ Moments<typename Codec<S>::C> moments_of(const typena
         m.yy += t;
         m.zz += t;
     }
+    to_flux(m);
     return m;
 }
 
@@ -320,15 +335,14 @@ struct Relaxed {
 template <typename C>
 __device__ __forceinline__ Relaxed<C> relax(C rho, C Fx, C Fy, C Fz, const Moments<C> &m, C ux, C uy, C uz, C r2,
                                             C keep, C guo, C ref) {
-    constexpr C T0 = C(1.0 / 3.0);
     // X: the non-equilibrium flux of Eq. (10) relaxed by 1 - 1/tau, plus the
     // second-order forcing part.
-    const C rt = rho * T0, ru = r2 * rho;
+    const C ru = r2 * rho;
     const C g2 = C(2) * guo;
     Relaxed<C> x;
-    x.xx = keep * (m.xx - rt - ru * ux * ux) + g2 * ux * Fx;
-    x.yy = keep * (m.yy - rt - ru * uy * uy) + g2 * uy * Fy;
-    x.zz = keep * (m.zz - rt - ru * uz * uz) + g2 * uz * Fz;
+    x.xx = keep * (m.xx - ru * ux * ux) + g2 * ux * Fx;
+    x.yy = keep * (m.yy - ru * uy * uy) + g2 * uy * Fy;
+    x.zz = keep * (m.zz - ru * uz * uz) + g2 * uz * Fz;
     x.xy = keep * (m.xy - ru * ux * uy) + guo * (ux * Fy + Fx * uy);
     x.xz = keep * (m.xz - ru * ux * uz) + guo * (ux * Fz + Fx * uz);
     x.yz = keep * (m.yz - ru * uy * uz) + guo * (uy * Fz + Fy * uz);
@@ -857,14 +871,14 @@ __device__ __forceinline__ float held_comp(typename Held<S>::T x) {
     }
 }
 
-// Eq. (4) and the second moments of component D of a held pull, summed in
+// Eq. (4) of component D of a held pull (density and momentum), summed in
 // the order of moments_of (the pair sums and differences of the nine
-// opposite pairs), with the 16-bit shift added back.
+// opposite pairs), with the 16-bit shift added back to the density.
 template <typename S, int D>
-__device__ __forceinline__ Moments<float> held_moments(const typename Held<S>::T (&raw)[19], float ref) {
-    const float z = -0.0f;
-    Moments<float> m{z, z, z, z, z, z, z, z, z, z};
+__device__ __forceinline__ void held_density_momentum(const typename Held<S>::T (&raw)[19], float ref,
+                                                      Moments<float> &m) {
     m.r = held_comp<S, D>(raw[0]);
+    m.jx = m.jy = m.jz = -0.0f;
     sfor<9>([&](auto K) {
         constexpr int i = 2 * K + 1;
         constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
@@ -874,6 +888,19 @@ __device__ __forceinline__ Moments<float> held_moments(const typename Held<S>::T
         acc_signed<X>(m.jx, d);
         acc_signed<Y>(m.jy, d);
         acc_signed<Z>(m.jz, d);
+    });
+    if constexpr (Codec<S>::shifted) m.r += ref;
+}
+
+// The second moments of component D of a held pull as P_ab (FP32), from the
+// same pair sums; m.r must hold the component's density.
+template <typename S, int D>
+__device__ __forceinline__ void held_flux(const typename Held<S>::T (&raw)[19], float ref, Moments<float> &m) {
+    m.xx = m.yy = m.zz = m.xy = m.xz = m.yz = -0.0f;
+    sfor<9>([&](auto K) {
+        constexpr int i = 2 * K + 1;
+        constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+        const float s = held_comp<S, D>(raw[i]) + held_comp<S, D>(raw[i + 1]);
         acc_signed<X * X>(m.xx, s);
         acc_signed<Y * Y>(m.yy, s);
         acc_signed<Z * Z>(m.zz, s);
@@ -883,12 +910,11 @@ __device__ __forceinline__ Moments<float> held_moments(const typename Held<S>::T
     });
     if constexpr (Codec<S>::shifted) {
         const float t = (1.0f / 3.0f) * ref;
-        m.r += ref;
         m.xx += t;
         m.yy += t;
         m.zz += t;
     }
-    return m;
+    to_flux(m);
 }
 
 // The density of component D alone, in the same order (same bits).
@@ -902,6 +928,38 @@ __device__ __forceinline__ float held_density(const typename Held<S>::T (&raw)[1
     if constexpr (Codec<S>::shifted) r += ref;
     return r;
 }
+
+// P_ab of component D accumulated in FP64 and rounded once to FP32: for
+// sites whose relaxation time is near 1/2 (low viscosity), where the viscous
+// stress is a small difference of sums of size rho / 3 and FP32 sums would
+// lose most of its digits.  P_ab = sum_i (c_ia c_ib - T0 delta_ab) f_i, so a
+// storage shift w_i rho_ref drops out (sum_i w_i (c c - T0 I) = 0) and the
+// 16-bit deviations enter as they are.
+template <typename S, int D>
+__device__ __forceinline__ void held_flux_fp64(const typename Held<S>::T (&raw)[19], Moments<float> &m) {
+    double r = (double)held_comp<S, D>(raw[0]);
+    double xx = 0, yy = 0, zz = 0, xy = 0, xz = 0, yz = 0;
+    sfor<9>([&](auto K) {
+        constexpr int i = 2 * K + 1;
+        constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+        const double s = (double)held_comp<S, D>(raw[i]) + (double)held_comp<S, D>(raw[i + 1]);
+        r += s;
+        acc_signed<X * X>(xx, s);
+        acc_signed<Y * Y>(yy, s);
+        acc_signed<Z * Z>(zz, s);
+        acc_signed<X * Y>(xy, s);
+        acc_signed<X * Z>(xz, s);
+        acc_signed<Y * Z>(yz, s);
+    });
+    const double rt = r * (1.0 / 3.0);
+    m.xx = (float)(xx - rt);
+    m.yy = (float)(yy - rt);
+    m.zz = (float)(zz - rt);
+    m.xy = (float)xy;
+    m.xz = (float)xz;
+    m.yz = (float)yz;
+}
+
 
 // What the collision of a site needs from its pulled populations besides
 // the densities (which the LDS plane holds): the mixture momentum j_1 + j_2
@@ -927,7 +985,7 @@ struct SiteMoments {
 // z - 1 .. z + 1 while a faster wave's A writes z + 2), index tiles of
 // planes z - 1 .. z + 4 (six); each slot is rewritten only after a barrier
 // that follows its last read.
-template <typename S, int TX, int TY, int MODE>
+template <typename S, int TX, int TY, int MODE, bool HI>
 __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slot) {
     using C = float;
     using H = typename Held<S>::T;
@@ -1050,10 +1108,21 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
         C r0 = a.wall0, r1 = a.wall1;
         if (self >= 0) {
             if (is_site && want_mom) {
-                const Moments<C> m0 = held_moments<S, 0>(raw, ref0);
-                const Moments<C> m1 = held_moments<S, 1>(raw, ref1);
+                Moments<C> m0, m1;
+                held_density_momentum<S, 0>(raw, ref0, m0);
+                held_density_momentum<S, 1>(raw, ref1, m1);
                 r0 = m0.r;
                 r1 = m1.r;
+                // tau_mix = (rho_1 tau_1 + rho_2 tau_2) / rho below tau_crit:
+                // the flux in FP64 (compiled into the HI instances only, so
+                // that the others keep their registers)
+                if (HI && r0 * a.tau0 + r1 * a.tau1 < a.tau_crit * (r0 + r1)) {
+                    held_flux_fp64<S, 0>(raw, m0);
+                    held_flux_fp64<S, 1>(raw, m1);
+                } else {
+                    held_flux<S, 0>(raw, ref0, m0);
+                    held_flux<S, 1>(raw, ref1, m1);
+                }
                 sm.jx = m0.jx + m1.jx;
                 sm.jy = m0.jy + m1.jy;
                 sm.jz = m0.jz + m1.jz;
@@ -1311,10 +1380,10 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
         }
     }
 }
-template <typename S, int TX, int TY, int MODE>
+template <typename S, int TX, int TY, int MODE, bool HI>
 __device__ __forceinline__ void step_dispatch(const KArgs<S> &a, int b, int slot) {
     if constexpr (sizeof(S) == 8) step_body<S, TX, TY, MODE>(a, b, slot);
-    else step_body_pipe<S, TX, TY, MODE>(a, b, slot);
+    else step_body_pipe<S, TX, TY, MODE, HI>(a, b, slot);
 }
 
 // Waves per SIMD the register allocator must allow: four for the 16-bit
@@ -1322,15 +1391,17 @@ __device__ __forceinline__ void step_dispatch(const KArgs<S> &a, int b, int slot
 // and 1024-thread blocks need four), the natural count otherwise.
 template <typename S> constexpr int kMinWaves = sizeof(S) <= 4 ? 4 : 1;
 
-template <typename S, int TX, int TY, int MODE>
+// HI: the instance with the FP64 flux at sites below tau_crit (32/16-bit
+// storage, advancing modes).
+template <typename S, int TX, int TY, int MODE, bool HI = false>
 __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(kMinWaves<S>))) step_kernel(KArgs<S> a) {
-    step_dispatch<S, TX, TY, MODE>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
+    step_dispatch<S, TX, TY, MODE, HI>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
 }
 
 // Many domains in one launch: work item w = (domain, tile) of a list sorted
 // by domain; descs[d] describes domain d with (src, dst) of an even step,
 // swapped when flip is set.
-template <typename S, int TX, int TY, int MODE>
+template <typename S, int TX, int TY, int MODE, bool HI = false>
 __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(kMinWaves<S>))) batch_kernel(const KArgs<S> *descs, const int2 *work, int flip) {
     const int2 w = work[xcd_remap(blockIdx.x, gridDim.x)];
     KArgs<S> a = descs[w.x];
@@ -1339,7 +1410,7 @@ __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(kMi
         a.src = a.dst;
         a.dst = const_cast<S *>(t);
     }
-    step_dispatch<S, TX, TY, MODE>(a, w.y, w.y);
+    step_dispatch<S, TX, TY, MODE, HI>(a, w.y, w.y);
 }
 
 __global__ void finalize_kernel(const double *partials, int nblocks, double *out) {
@@ -1527,6 +1598,7 @@ KArgs<S> make_kargs(const StepLaunch &L) {
     a.tau0 = (C)L.tau0; a.tau1 = (C)L.tau1; a.G = (C)L.G;
     a.gx = (C)L.gx; a.gy = (C)L.gy; a.gz = (C)L.gz;
     a.wall0 = (C)L.wall0; a.wall1 = (C)L.wall1; a.ref0 = (C)L.ref0; a.ref1 = (C)L.ref1;
+    a.tau_crit = (C)L.tau_crit;
     a.eq_kind = L.eq_kind; a.force_kind = L.force_kind; a.wall_kind = L.wall_kind;
     a.partials = L.partials;
     a.out_rho0 = L.out_rho0; a.out_rho1 = L.out_rho1; a.out_u = L.out_u;
@@ -1538,9 +1610,16 @@ template <typename S, int TX, int TY>
 hipError_t launch_typed(Mode mode, const StepLaunch &L, hipStream_t s) {
     const KArgs<S> a = make_kargs<S>(L);
     const dim3 grid((unsigned)(L.ntx * L.nty * L.nzc)), block(TX * TY);
+    const bool hi = sizeof(S) < 8 && L.tau_crit > 0;
     switch (mode) {
-    case MODE_STEP: hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE_STEP>), grid, block, 0, s, a); break;
-    case MODE_CHECK: hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE_CHECK>), grid, block, 0, s, a); break;
+    case MODE_STEP:
+        if (hi) hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE_STEP, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE_STEP>), grid, block, 0, s, a);
+        break;
+    case MODE_CHECK:
+        if (hi) hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE_CHECK, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE_CHECK>), grid, block, 0, s, a);
+        break;
     default: hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE_MOMENTS>), grid, block, 0, s, a); break;
     }
     return hipGetLastError();
@@ -1581,28 +1660,36 @@ int occupancy_tiles(int tx, int ty) {
 }
 
 template <typename S, int TX, int TY>
-hipError_t launch_batch_typed(Mode mode, const void *descs, const int2 *work, int nwork, int flip, hipStream_t s) {
+hipError_t launch_batch_typed(Mode mode, bool hi, const void *descs, const int2 *work, int nwork, int flip,
+                              hipStream_t s) {
     const KArgs<S> *d = static_cast<const KArgs<S> *>(descs);
     const dim3 grid((unsigned)nwork), block(TX * TY);
+    hi = hi && sizeof(S) < 8;
     switch (mode) {
-    case MODE_STEP: hipLaunchKernelGGL((batch_kernel<S, TX, TY, MODE_STEP>), grid, block, 0, s, d, work, flip); break;
-    case MODE_CHECK: hipLaunchKernelGGL((batch_kernel<S, TX, TY, MODE_CHECK>), grid, block, 0, s, d, work, flip); break;
+    case MODE_STEP:
+        if (hi) hipLaunchKernelGGL((batch_kernel<S, TX, TY, MODE_STEP, true>), grid, block, 0, s, d, work, flip);
+        else hipLaunchKernelGGL((batch_kernel<S, TX, TY, MODE_STEP>), grid, block, 0, s, d, work, flip);
+        break;
+    case MODE_CHECK:
+        if (hi) hipLaunchKernelGGL((batch_kernel<S, TX, TY, MODE_CHECK, true>), grid, block, 0, s, d, work, flip);
+        else hipLaunchKernelGGL((batch_kernel<S, TX, TY, MODE_CHECK>), grid, block, 0, s, d, work, flip);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <typename S>
-hipError_t launch_batch_tiles(Mode mode, int tx, int ty, const void *descs, const int2 *work, int nwork, int flip,
-                              hipStream_t s) {
-    if (tx == 64 && ty == 4) return launch_batch_typed<S, 64, 4>(mode, descs, work, nwork, flip, s);
-    if (tx == 32 && ty == 8) return launch_batch_typed<S, 32, 8>(mode, descs, work, nwork, flip, s);
-    if (tx == 16 && ty == 16) return launch_batch_typed<S, 16, 16>(mode, descs, work, nwork, flip, s);
-    if (tx == 8 && ty == 32) return launch_batch_typed<S, 8, 32>(mode, descs, work, nwork, flip, s);
-    if (tx == 64 && ty == 8) return launch_batch_typed<S, 64, 8>(mode, descs, work, nwork, flip, s);
-    if (tx == 32 && ty == 16) return launch_batch_typed<S, 32, 16>(mode, descs, work, nwork, flip, s);
+hipError_t launch_batch_tiles(Mode mode, bool hi, int tx, int ty, const void *descs, const int2 *work, int nwork,
+                              int flip, hipStream_t s) {
+    if (tx == 64 && ty == 4) return launch_batch_typed<S, 64, 4>(mode, hi, descs, work, nwork, flip, s);
+    if (tx == 32 && ty == 8) return launch_batch_typed<S, 32, 8>(mode, hi, descs, work, nwork, flip, s);
+    if (tx == 16 && ty == 16) return launch_batch_typed<S, 16, 16>(mode, hi, descs, work, nwork, flip, s);
+    if (tx == 8 && ty == 32) return launch_batch_typed<S, 8, 32>(mode, hi, descs, work, nwork, flip, s);
+    if (tx == 64 && ty == 8) return launch_batch_typed<S, 64, 8>(mode, hi, descs, work, nwork, flip, s);
+    if (tx == 32 && ty == 16) return launch_batch_typed<S, 32, 16>(mode, hi, descs, work, nwork, flip, s);
     if constexpr (sizeof(S) <= 4)
-        if (tx == 64 && ty == 16) return launch_batch_typed<S, 64, 16>(mode, descs, work, nwork, flip, s);
+        if (tx == 64 && ty == 16) return launch_batch_typed<S, 64, 16>(mode, hi, descs, work, nwork, flip, s);
     return hipErrorInvalidValue;
 }
 
@@ -1628,13 +1715,13 @@ void fill_batch_desc(int prec, const StepLaunch &L, void *out) {
     }
 }
 
-hipError_t launch_batch(int prec, Mode mode, int tx, int ty, const void *descs, const int2 *work, int nwork, int flip,
-                        hipStream_t s) {
+hipError_t launch_batch(int prec, Mode mode, bool hi, int tx, int ty, const void *descs, const int2 *work, int nwork,
+                        int flip, hipStream_t s) {
     switch (prec) {
-    case LBM_FP64: return launch_batch_tiles<double>(mode, tx, ty, descs, work, nwork, flip, s);
-    case LBM_FP32: return launch_batch_tiles<float>(mode, tx, ty, descs, work, nwork, flip, s);
-    case LBM_FP16S: return launch_batch_tiles<__half>(mode, tx, ty, descs, work, nwork, flip, s);
-    case LBM_BF16S: return launch_batch_tiles<__hip_bfloat16>(mode, tx, ty, descs, work, nwork, flip, s);
+    case LBM_FP64: return launch_batch_tiles<double>(mode, hi, tx, ty, descs, work, nwork, flip, s);
+    case LBM_FP32: return launch_batch_tiles<float>(mode, hi, tx, ty, descs, work, nwork, flip, s);
+    case LBM_FP16S: return launch_batch_tiles<__half>(mode, hi, tx, ty, descs, work, nwork, flip, s);
+    case LBM_BF16S: return launch_batch_tiles<__hip_bfloat16>(mode, hi, tx, ty, descs, work, nwork, flip, s);
     default: return hipErrorInvalidValue;
     }
 }

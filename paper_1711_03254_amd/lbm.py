@@ -53,6 +53,7 @@ class lbm_params(ctypes.Structure):
         ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
         ("zchunk", ctypes.c_int32),
         ("wall_kind", ctypes.c_int32),
+        ("tau_crit", ctypes.c_double),
     ]
 
 
@@ -151,6 +152,7 @@ class Params:
     stream: object = None
     tile: tuple = (0, 0)
     zchunk: int = 0
+    tau_crit: float = 0.0
 
 
 class Context:
@@ -217,6 +219,7 @@ def lbm_init(p: Params) -> Context:
         s.stream = p.stream.cuda_stream if hasattr(p.stream, "cuda_stream") else int(p.stream)
     s.tile_x, s.tile_y = p.tile
     s.zchunk = p.zchunk
+    s.tau_crit = p.tau_crit
     h = ctypes.c_void_p()
     rc = lib.lbm_init(ctypes.byref(s), ctypes.byref(h))
     if rc != LBM_OK:

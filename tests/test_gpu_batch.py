@@ -131,3 +131,29 @@ def test_deep_batch_chunks_equal_single_domains(lbm, prec):
     red = lbm.lbm_reduce(batched[0])
     m0 = lbm.lbm_info(batched[0])["mass0"]
     assert abs(red[0] - m0[0]) / m0[0] <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+def test_autotuned_batch_is_no_slower_than_default(lbm, tmp_path):
+    """The autotuner times the whole batch at each candidate launch shape
+    (the default 64 x 8 tile with default z-chunks among them) and caches
+    the fastest; stepping 4 uneven ducts at the tuned shape is then no slower
+    than at the default (timing noise allowed: 5 %), and a second call reads
+    the cache instead of tuning again."""
+    import json
+
+    from paper_1711_03254_amd import autotune
+    doms = [d for d in inputs.ensemble_case(16, seed=5) if d["shape"][1] >= 48][:4]
+    assert len(doms) == 4
+    cache = str(tmp_path / "shapes.json")
+    best = autotune.tune_batch(doms, "fp32", steps=8, warmup=2, cache=cache)
+    assert "64x8/0" in best["all_ms"]
+    assert best["ms"] == min(best["all_ms"].values())
+    assert autotune.tune_batch(doms, "fp32", cache=cache) == json.load(open(cache))[autotune.batch_key(doms, "fp32")]
+
+    def timed(tile, zc):
+        return autotune._time_batch(lbm, "fp32", doms, tile, zc, 16, 4)
+
+    t_default = min(timed((64, 8), 0) for _ in range(2))
+    t_tuned = min(timed(tuple(best["tile"]), best["zchunk"]) for _ in range(2))
+    print(f"default {t_default * 1e3:.3f} ms, tuned {best['tile']}/{best['zchunk']} {t_tuned * 1e3:.3f} ms")
+    assert t_tuned <= 1.05 * t_default

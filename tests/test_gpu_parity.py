@@ -4,15 +4,14 @@ Tolerances: populations and densities in the normalized max-norm
 max|X_gpu - X_oracle| / max|X_oracle|; the velocity u_F as an absolute error
 in lattice units (its scale is the lattice speed; normalizing by max |u_F|
 would divide by a spurious current of 1e-3 in a static droplet).
-FP64 storage and arithmetic 1e-12; FP32 1e-5 up to ten steps.  The FP64
+FP64 storage and arithmetic 1e-12 at every horizon; FP32 1e-5.  The FP64
 kernel and the oracle evaluate the same equations in a different order (and
 with fused multiply-adds on the GPU), so they agree to rounding, about 1e-15
-per step.  FP32 rounds every stored population to single precision (relative
-2^-24) and computes in FP32, so over n steps a deviation can grow to about
-n * 2 * 2^-24 of the population scale.  Longer FP32 runs use that bound: for
-the densities relative to their maximum, and for u_F as an absolute error in
-lattice units (u_F = j / rho inherits the absolute rounding of j, not a
-rounding relative to max |u_F|, which may be a tiny spurious current).
+per step.  FP32 rounds every stored population to single precision and
+computes in FP32: it meets 1e-5 on the macroscopic fields up to a measured
+horizon (FP32_HORIZON steps of the droplet, 40 steps with walls); where it
+does not (the 500-step droplet, the 20000-step channel at tau = 0.5051) the
+tests say so and guard the measured figure against regressions instead.
 Measured deviations are appended to $PARITY_LOG (JSON lines) when it is set.
 """
 import json
@@ -26,10 +25,6 @@ from paper_1711_03254_amd import inputs
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
-
-
-def fp32_bound(steps):
-    return max(1e-5, steps * 2 * 2.0 ** -24)
 
 
 def record(name, **vals):
@@ -130,7 +125,7 @@ def test_momentum_balanced_walls(lbm, ora, prec, tile, rho_s):
     devs = [nmax(m[0], want[0]), nmax(m[1], want[1]), nmax(m[2], want[2])]
     record("walls_w2", prec=prec, tile=list(tile), rho_s=rho_s, one_step=dev1, moments40=devs)
     assert dev1 <= TOL[prec]
-    assert max(devs) <= (TOL[prec] if prec == "fp64" else fp32_bound(40))
+    assert max(devs) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -166,21 +161,50 @@ def test_init_equals_oracle_equilibrium(lbm, ora, eq_kind):
     assert nmax(lbm.lbm_get_populations(ctx), ora.init(p, r1, r2, u)) <= 1e-14
 
 
+# Longest horizon (steps) of the 32^3 droplet at which FP32 meets the 1e-5
+# bar on rho_1, rho_2 (normalized) and u_F (absolute); measured, see below.
+FP32_HORIZON = 200
+
+
+@pytest.fixture(scope="module")
+def droplet_horizons(ora, droplet_reference):
+    rA, rB, p, ref, _ = droplet_reference
+    f = ora.init(p, rA, rB)
+    out, done = {}, 0
+    for t in (10, 50, 100, 200, 500):
+        f = ora.run(p, f, t - done)
+        done = t
+        out[t] = ora.moments(p, f)
+    return out
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_droplet_500_steps(lbm, droplet_reference, prec):
+def test_droplet_500_steps(lbm, droplet_reference, droplet_horizons, prec):
+    """The 32^3 droplet (C1) against the oracle at 10, 50, 100, 200 and 500
+    steps.  FP64: 1e-12 at every horizon.  FP32: the 1e-5 bar at every
+    horizon up to FP32_HORIZON steps, where it holds (measured 5.5e-6 at 200
+    steps); beyond it the densities drift past 1e-5 (1.4e-5 at 500 steps:
+    the rounding of the stored populations accumulates in the slowly
+    relaxing interface), so the 500-step figure is asserted against about
+    twice its measured value as a regression guard, not as the bar."""
     rA, rB, p, ref, (red0, red500) = droplet_reference
     ctx = lbm.lbm_init(lbm.Params(32, 32, 32, prec=lbm.PRECISIONS[prec], tau=p.tau, G=p.G, rho_init=(rA, rB),
                                   check_every=50))
-    lbm.lbm_step(ctx, 10)
-    d10 = [nmax(k, o) for k, o in zip(lbm.lbm_moments(ctx), ref[10])]
-    lbm.lbm_step(ctx, 490)
-    got = lbm.lbm_moments(ctx)
-    d500 = [nmax(k, o) for k, o in zip(got, ref[500])]
-    uabs = float(np.abs(got[2] - ref[500][2]).max())
-    record("droplet_32", prec=prec, dev10=d10, dev500=d500, u_abs500=uabs)
-    assert max(d10) <= TOL[prec]
-    bound = TOL[prec] if prec == "fp64" else fp32_bound(500)
-    assert max(d500[:2]) <= bound and uabs <= bound
+    devs, done = {}, 0
+    for t in (10, 50, 100, 200, 500):
+        lbm.lbm_step(ctx, t - done)
+        done = t
+        got = lbm.lbm_moments(ctx)
+        want = droplet_horizons[t]
+        devs[t] = [nmax(got[0], want[0]), nmax(got[1], want[1]), float(np.abs(got[2] - want[2]).max())]
+    record("droplet_32", prec=prec, dev={str(k): v for k, v in devs.items()})
+    for t, d in devs.items():
+        if prec == "fp64":
+            assert max(d) <= TOL["fp64"], (t, d)
+        elif t <= FP32_HORIZON:
+            assert max(d) <= TOL["fp32"], (t, d)
+    if prec == "fp32":
+        assert max(devs[500]) <= 3e-5, devs[500]
     red = lbm.lbm_reduce(ctx)
     # mass conservation: FP64 to rounding, FP32 to its storage precision
     drift = np.abs(red[:2] - red0[:2]) / red0[:2]
@@ -308,15 +332,40 @@ def test_device_pointers_and_stream(lbm, ora):
     assert np.array_equal(fd.cpu().numpy(), lbm.lbm_get_populations(ctx))
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+# Arms of the 20000-step channel: storage precision and tau_crit (sites whose
+# mixture relaxation time is below it form the collision's second moments in
+# FP64; 0.55 covers the low-viscosity layer, tau = 0.5051).
+CHANNEL_ARMS = {"fp64": ("fp64", 0.0), "fp32": ("fp32", 0.0), "fp32_fp64flux": ("fp32", 0.55),
+                "fp16s": ("fp16s", 0.0), "fp16s_fp64flux": ("fp16s", 0.55)}
+_channel_oracle = {}
+
+
+@pytest.mark.parametrize("arm", list(CHANNEL_ARMS))
 @pytest.mark.parametrize("nuA,nuB", [(0.0017, 1.7), (1.7, 0.0017), (0.0017, 0.17), (0.0017, 0.017)])
-def test_two_layer_channel_20000_steps(lbm, ora, prec, nuA, nuB):
+def test_two_layer_channel_20000_steps(lbm, ora, arm, nuA, nuB):
     """The two-layer channel workload: 8 x 64 x 256, walls at y = 0 and 63,
     A in y = 1..31 and B in y = 32..62 with minority densities near their
     coexistence value, g = 1e-6 along z, G = -4.2, viscosity ratios 1000,
     1/1000, 100 and 10 with the lower viscosity 0.0017 (tau = 0.5051),
     20000 steps.  The state stays uniform in x and z, so the oracle runs the
-    exactly equivalent 1 x 64 x 1 column."""
+    exactly equivalent 1 x 64 x 1 column.
+
+    FP64 matches to 1e-12.  FP32 does not meet the 1e-5 bar at this horizon
+    (densities 3.7e-4 to 5.8e-4 off, normalized; u_F 4e-6 to 1e-5 in lattice
+    units): at tau = 0.5051 the collision maps the non-equilibrium part to
+    1 - 1/tau = -0.98 times itself, so the rounding of the stored populations
+    is hardly damped, and the flow develops over a viscous time far beyond
+    20000 steps.  Forming the collision's second moments in FP64
+    (tau_crit = 0.55, the low-viscosity layer) changes these figures by a few
+    per cent either way: the storage rounding, not the arithmetic, sets them.
+    FP16S fails here outright (densities 11-20 % off, u_F wrong by its own
+    size, component masses drifting by up to 11 %, so its periodic check
+    runs with a tolerance of 1): each component's density is 1 in its layer
+    and 0.005 in the other, so its deviation from the one shift reference is
+    half its density everywhere and FP16 keeps 11 bits of that.  The figures are asserted
+    against about twice their measured values, as regression guards, and
+    recorded (PARITY_LOG)."""
+    prec, tau_crit = CHANNEL_ARMS[arm]
     T0 = 1.0 / 3.0
     nz, ny, nx = 256, 64, 8
     kw = dict(tau=(nuA / T0 + 0.5, nuB / T0 + 0.5), G=-4.2, g=(0.0, 0.0, 1e-6))
@@ -325,26 +374,39 @@ def test_two_layer_channel_20000_steps(lbm, ora, prec, nuA, nuB):
     r1, r2 = inputs.two_layer((1, ny, 1), 1.0, 0.005)
     r1[col == 1] = 0
     r2[col == 1] = 0
-    ora.set_threads(1)
-    p = ora.Params(1, ny, 1, solid=col, **kw)
-    o1, o2, ou = ora.moments(p, ora.run(p, ora.init(p, r1, r2), 20000))
-    ora.set_threads(8)
+    if (nuA, nuB) not in _channel_oracle:
+        ora.set_threads(1)
+        p = ora.Params(1, ny, 1, solid=col, **kw)
+        _channel_oracle[(nuA, nuB)] = ora.moments(p, ora.run(p, ora.init(p, r1, r2), 20000))
+        ora.set_threads(8)
+    o1, o2, ou = _channel_oracle[(nuA, nuB)]
     shape = (nz, ny, nx)
     solid = np.broadcast_to(col, shape).copy()
     ctx = lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=solid,
                                   rho_init=(np.broadcast_to(r1, shape).copy(), np.broadcast_to(r2, shape).copy()),
-                                  check_every=1000, **kw))
+                                  check_every=1000, tau_crit=tau_crit,
+                                  mass_tol=0.0 if prec in ("fp64", "fp32") else 1.0, **kw))
+    m0 = lbm.lbm_info(ctx)["mass0"]
     lbm.lbm_step(ctx, 20000)
     g1, g2, gu = lbm.lbm_moments(ctx)
+    red = lbm.lbm_reduce(ctx)
+    drift = [abs(red[k] - m0[k]) / m0[k] for k in range(2)]
     devs = [nmax(g1, np.broadcast_to(o1, shape)), nmax(g2, np.broadcast_to(o2, shape)),
             nmax(gu, np.broadcast_to(ou, (3,) + shape))]
     # x and z stay uniform on the GPU too
     spread = float(np.abs(gu[2] - gu[2][:1, :, :1]).max() / np.abs(gu[2]).max())
     uabs = float(np.abs(gu - np.broadcast_to(ou, (3,) + shape)).max())
-    record("channel_8x64x256", prec=prec, nuA=nuA, nuB=nuB, dev=devs, u_abs=uabs, xz_spread=spread)
-    bound = TOL[prec] if prec == "fp64" else fp32_bound(20000)
-    assert max(devs[:2]) <= bound and uabs <= bound
-    assert spread <= (1e-13 if prec == "fp64" else 1e-5)
+    record("channel_8x64x256", arm=arm, prec=prec, tau_crit=tau_crit, nuA=nuA, nuB=nuB, dev=devs, u_abs=uabs,
+           xz_spread=spread, mass_drift=drift)
+    assert np.isfinite(gu).all()
+    if prec == "fp64":
+        assert max(devs[:2]) <= TOL["fp64"] and uabs <= TOL["fp64"]
+        assert spread <= 1e-13
+    elif prec == "fp32":
+        assert max(devs[:2]) <= 1.2e-3 and uabs <= 2e-5   # regression guard; not the 1e-5 bar (see above)
+        assert spread <= 1e-5
+    else:
+        assert max(devs[:2]) <= 0.4 and uabs <= 0.04      # regression guard; the form fails this case
 
 
 @pytest.fixture(scope="module")
@@ -358,22 +420,23 @@ def packed_spheres():
     return solid, rA, rB, phys
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16s"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s", "bf16s"])
 def test_full_size_sampled_sites(lbm, ora, packed_spheres, prec):
     """At the benchmark's full size and launch configuration (default tile
     and z-chunk), two steps: the first from the known initial state, the
     second from the GPU's own state after one step.  4000 seeded fluid sites
     (half of them next to a wall) are recomputed one by one by the oracle.
-    FP16S: each stored population carries one rounding of its deviation
-    f - w rho_ref (relative 2^-11, the deviation at most max |f|) on entry
-    and on store, and the entry rounding propagates through the step: bound
-    4 x 2^-11 of max |f| (as for the one-step 16-bit test)."""
+    FP64 to 1e-12, FP32 to 1e-5.  FP16S and BF16S: each stored population
+    carries one rounding of its deviation f - w rho_ref (relative 2^-11 or
+    2^-8, the deviation at most max |f|) on entry and on store, and the entry
+    rounding propagates through the step: bound 4 x 2^-11 or 4 x 2^-8 of
+    max |f| (as for the one-step 16-bit test)."""
     import torch
     solid, rA, rB, phys = packed_spheres
     n = solid.shape[0]
     ctx = lbm.lbm_init(lbm.Params(n, n, n, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(rA, rB),
                                   check_every=100, **phys))
-    tol = TOL["fp32"] if prec == "fp32" else 4 * 2.0 ** -11
+    tol = {"fp64": TOL["fp64"], "fp32": TOL["fp32"], "fp16s": 4 * 2.0 ** -11, "bf16s": 4 * 2.0 ** -8}[prec]
     p = ora.Params(n, n, n, solid=solid, **phys)
     fluid = np.flatnonzero(solid.ravel() == 0)
     near = np.zeros(solid.shape, bool)
@@ -398,3 +461,42 @@ def test_full_size_sampled_sites(lbm, ora, packed_spheres, prec):
         if step == 0:
             f_prev = fd.cpu().numpy()
     del fd
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s", "bf16s"])
+def test_resume_into_placeholder_context(lbm, prec):
+    """A checkpoint resumed into a context created from placeholder fields
+    (uniform densities far from the state's): the periodic mass check then
+    compares against the resumed state's masses (no false drift error), at
+    16 bits the default shift becomes the resumed state's mean density, and
+    the run continues as the original context's does -- bit for bit at FP64
+    and FP32, within the storage rounding at 16 bits."""
+    shape = (18, 20, 26)
+    nz, ny, nx = shape
+    solid = np.zeros(shape, np.uint8)
+    solid[:, 0, :] = 1
+    rA, rB = inputs.droplet(shape, 5.0, center=(13.0, 10.0, 9.0))
+    rA[solid == 1] = 0
+    rB[solid == 1] = 0
+    kw = dict(prec=lbm.PRECISIONS[prec], solid=solid, tau=(0.8, 1.2), G=-3.0, g=(0.0, 0.0, 1e-5), rho_s=0.2,
+              check_every=5, mass_tol=1e-6 if prec in ("fp64", "fp32") else 1e-2)
+    a = lbm.lbm_init(lbm.Params(nx, ny, nz, rho_init=(rA, rB), **kw))
+    lbm.lbm_step(a, 10)
+    mid = lbm.lbm_get_populations(a)
+    lbm.lbm_step(a, 20)
+    end_a = lbm.lbm_moments(a)
+    ph = np.where(solid == 1, 0.0, 5.0)
+    b = lbm.lbm_init(lbm.Params(nx, ny, nz, rho_init=(ph, ph.copy()), **kw))
+    lbm.lbm_set_populations(b, mid)
+    mass_mid = [float(mid[d][:, solid == 0].sum()) for d in range(2)]
+    m0 = lbm.lbm_info(b)["mass0"]
+    # the check sums densities formed in the storage's arithmetic (FP32 at FP32)
+    np.testing.assert_allclose(m0, mass_mid, rtol={"fp64": 1e-12, "fp32": 1e-6}.get(prec, 2e-3))
+    lbm.lbm_step(b, 20)   # periodic checks against the resumed masses
+    end_b = lbm.lbm_moments(b)
+    devs = [nmax(x, y) for x, y in zip(end_b, end_a)]
+    record("resume_placeholder", prec=prec, dev=devs)
+    if prec in ("fp64", "fp32"):
+        assert all(np.array_equal(x, y) for x, y in zip(end_b, end_a))
+    else:
+        assert max(devs[:2]) <= 8 * (2.0 ** -11 if prec == "fp16s" else 2.0 ** -8)
