@@ -163,6 +163,29 @@ int lbm_set_populations(lbm_ctx *c, const double *f, int on_device);
  * u may be NULL (rest).  Component masses for the check are re-recorded. */
 int lbm_set_fields(lbm_ctx *c, const double *rho1, const double *rho2, const double *u, int on_device);
 
+/* Warm start with a non-equilibrium part: as lbm_set_fields, plus the part
+ * of the populations that the strain of u implies to first order in the
+ * Chapman-Enskog expansion (the moment behind the regularization of
+ * Eq. 10): Pi = -rho T0 tau_mix (grad u + grad u^T) with tau_mix of
+ * Eqs. (5-6), shared by the components in proportion to their densities
+ * and projected as in Eq. (10).  grad u takes central differences, with a
+ * solid neighbour standing for a wall half a site away where u = 0.
+ * u (3N) is required.  Allocates and frees a 6N-double work buffer.
+ * Errors: LBM_EINVAL (NULL argument or invalid fields), LBM_ENOMEM,
+ * LBM_EDEVICE. */
+int lbm_set_fields_strain(lbm_ctx *c, const double *rho1, const double *rho2, const double *u, int on_device);
+
+/* Convergence residual of a steady solve, in FP64 on the device:
+ * out[0] = ||u_F - u_F'|| / ||u_F||, out[1] = ||rho1 - rho1'|| / ||rho1||
+ * (2-norms over the lattice; u_F of Eq. 8), where the primed fields are
+ * those of the previous lbm_residual call on this context, or zero after
+ * lbm_init, lbm_set_fields(_strain) and lbm_set_populations (the first
+ * call then gives 1).  Keeps the current fields as the next call's primed
+ * ones (4N doubles held by the context from the first call).  A zero norm
+ * with a zero difference gives 0.  Synchronizes the context's stream.
+ * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE. */
+int lbm_residual(lbm_ctx *c, double out[2]);
+
 /* Facts about a context, for reports: number of fluid sites, steps done,
  * bytes of population storage per site update (read + write), and the
  * step kernel's launch configuration. */

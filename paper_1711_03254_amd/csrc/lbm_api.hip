@@ -29,6 +29,8 @@ struct lbm_ctx {
     double *red_dev = nullptr;
     double *red_host = nullptr;   // pinned
     double *stage = nullptr;      // 5N doubles, allocated on first use
+    double *snap = nullptr;       // 4N doubles: rho1 and u_F of the last lbm_residual (first use)
+    bool snap_valid = false;      // false: the snapshot is cleared before the next residual
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
@@ -247,8 +249,9 @@ int validate_fields(lbm_ctx *c, const uint8_t *solid_h, const double *r0, const 
 }
 
 // Copies the field arrays to the device staging buffer (when they are on
-// the host), validates them, and sets the state to their equilibrium.
-int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u, int on_device) {
+// the host), validates them, and sets the state to their equilibrium, plus
+// (strain) the non-equilibrium part that the velocity field's strain implies.
+int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u, int on_device, bool strain = false) {
     const size_t NB = sizeof(double) * (size_t)c->N;
     std::vector<double> h0, h1, hu;
     std::vector<uint8_t> hs;
@@ -294,9 +297,28 @@ int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u,
     HIPCHK(c, hipMemcpyAsync(c->stage, vr0, NB, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->stage + c->N, vr1, NB, hipMemcpyHostToDevice, c->stream));
     if (vu) HIPCHK(c, hipMemcpyAsync(c->stage + 2 * c->N, vu, 3 * NB, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, lbm::launch_init_fields(c->p.prec, c->f[c->cur], c->links, c->idx, c->stage, c->stage + c->N,
-                                      vu ? c->stage + 2 * c->N : nullptr, c->p.nx, c->p.ny, c->p.nz, c->ngroups,
-                                      c->p.eq_kind, c->ref, c->stream));
+    double *pi = nullptr;
+    if (strain && vu) {
+        if (hipMalloc(&pi, 6 * NB) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, LBM_ENOMEM, "cannot allocate the 6N-double strain buffer");
+        }
+        hipError_t e = lbm::launch_strain(c->links, c->stage, c->stage + c->N, c->stage + 2 * c->N, c->p.tau[0],
+                                          c->p.tau[1], c->p.nx, c->p.ny, c->p.nz, pi, c->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(pi);
+            return fail(c, LBM_EDEVICE, std::string("strain: ") + hipGetErrorString(e));
+        }
+    }
+    hipError_t e = lbm::launch_init_fields(c->p.prec, c->f[c->cur], c->links, c->idx, c->stage, c->stage + c->N,
+                                           vu ? c->stage + 2 * c->N : nullptr, pi, c->p.nx, c->p.ny, c->p.nz,
+                                           c->ngroups, c->p.eq_kind, c->ref, c->stream);
+    if (pi) {
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(pi);
+    }
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("init_fields: ") + hipGetErrorString(e));
+    c->snap_valid = false;
     rc = measure(c, nullptr, nullptr, nullptr);
     if (rc) return rc;
     c->mass0[0] = c->red_host[0];
@@ -384,7 +406,7 @@ void release(lbm_ctx *c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (void *q : {c->f[0], c->f[1], (void *)c->links, (void *)c->idx, (void *)c->wstart, (void *)c->wpos,
-                    (void *)c->partials, (void *)c->red_dev, (void *)c->stage})
+                    (void *)c->partials, (void *)c->red_dev, (void *)c->stage, (void *)c->snap})
         if (q) (void)hipFree(q);
     if (c->red_host) (void)hipHostFree(c->red_host);
     for (int k = 0; k < 2; ++k) {
@@ -769,6 +791,7 @@ int lbm_set_populations(lbm_ctx *c, const double *f, int on_device) {
     if (!on_device) (void)hipFree(src);
     if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("set_populations: ") + hipGetErrorString(e));
     if (rc) return rc;
+    c->snap_valid = false;
     // The periodic check compares against the masses of the resumed state.
     rc = measure(c, nullptr, nullptr, nullptr);
     if (rc) return rc;
@@ -781,6 +804,55 @@ int lbm_set_fields(lbm_ctx *c, const double *rho1, const double *rho2, const dou
     if (!c || !rho1 || !rho2) return fail(c, LBM_EINVAL, "lbm_set_fields: NULL argument");
     HIPCHK(c, hipSetDevice(c->device));
     return load_fields(c, rho1, rho2, u, on_device);
+}
+
+int lbm_set_fields_strain(lbm_ctx *c, const double *rho1, const double *rho2, const double *u, int on_device) {
+    if (!c || !rho1 || !rho2 || !u) return fail(c, LBM_EINVAL, "lbm_set_fields_strain: NULL argument");
+    HIPCHK(c, hipSetDevice(c->device));
+    return load_fields(c, rho1, rho2, u, on_device, true);
+}
+
+int lbm_residual(lbm_ctx *c, double out[2]) {
+    if (!c || !out) return fail(c, LBM_EINVAL, "lbm_residual: NULL argument");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = ensure_stage(c);
+    if (rc) return rc;
+    const size_t NB = sizeof(double) * (size_t)c->N;
+    if (!c->snap) {
+        if (hipMalloc(&c->snap, 4 * NB) != hipSuccess) {
+            c->snap = nullptr;
+            (void)hipGetLastError();
+            return fail(c, LBM_ENOMEM, "cannot allocate the 4N-double residual snapshot");
+        }
+        c->snap_valid = false;
+    }
+    if (!c->snap_valid) HIPCHK(c, hipMemsetAsync(c->snap, 0, 4 * NB, c->stream));
+    // rho1 at stage[0, N), u_F at stage[2N, 5N); solid sites stay 0.
+    double *ra = c->stage, *u = c->stage + 2 * c->N;
+    HIPCHK(c, hipMemsetAsync(ra, 0, NB, c->stream));
+    HIPCHK(c, hipMemsetAsync(u, 0, 3 * NB, c->stream));
+    lbm::StepLaunch L = make_launch(c, c->f[c->cur], nullptr);
+    L.out_rho0 = ra;
+    L.out_u = u;
+    HIPCHK(c, lbm::launch_step(c->p.prec, lbm::MODE_MOMENTS, L, c->stream));
+    const int nb = std::min<int64_t>(nblocks(c), std::max<int64_t>(1, (c->N + 255) / 256));
+    HIPCHK(c, lbm::launch_residual(ra, u, c->snap, c->snap + c->N, c->N, nb, c->partials, c->stream));
+    HIPCHK(c, lbm::launch_finalize(c->partials, nb, c->red_dev, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->red_host, c->red_dev, sizeof(double) * lbm::kPartialStride, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->snap, ra, NB, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->snap + c->N, u, 3 * NB, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->snap_valid = true;
+    auto rel = [](double diff2, double norm2) {
+        if (norm2 > 0) return std::sqrt(diff2 / norm2);
+        return diff2 > 0 ? HUGE_VAL : 0.0;
+    };
+    out[0] = rel(c->red_host[2], c->red_host[3]);
+    out[1] = rel(c->red_host[0], c->red_host[1]);
+    if (!std::isfinite(c->red_host[0] + c->red_host[1] + c->red_host[2] + c->red_host[3]))
+        return fail(c, LBM_ENONFINITE, "lbm_residual: non-finite fields");
+    return LBM_OK;
 }
 
 int lbm_info(const lbm_ctx *c, lbm_info_t *out) {

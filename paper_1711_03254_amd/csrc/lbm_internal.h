@@ -60,12 +60,21 @@ hipError_t launch_step(int prec, Mode mode, const StepLaunch &L, hipStream_t s);
 hipError_t launch_finalize(const double *partials, int nblocks, double *out, hipStream_t s);
 // Per-site link mask: bit 0 = site solid, bit i = site - c_i solid (periodic).
 hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, int nz, hipStream_t s);
-// Internal state from fields: f*_j(x) = f_eq,j(x + c_j) if that site is fluid,
-// else f_eq,opp(j)(x); f_eq from rho (2N), u (3N or null).  Populations of
-// fluid site s are at slot idx[s].
+// Internal state from fields: f*_j(x) = f_j(x + c_j) if that site is fluid,
+// else f_opp(j)(x), with f = f_eq from rho (2N), u (3N or null), plus the
+// strain's non-equilibrium part when pi (6N, launch_strain) is given.
+// Populations of fluid site s are at slot idx[s].
 hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
-                              const double *rho1, const double *u, int nx, int ny, int nz, int64_t ngroups,
-                              int eq_kind, const double ref[2], hipStream_t s);
+                              const double *rho1, const double *u, const double *pi, int nx, int ny, int nz,
+                              int64_t ngroups, int eq_kind, const double ref[2], hipStream_t s);
+// Pi / rho of the warm start's non-equilibrium part (6N: xx, yy, zz, xy, xz,
+// yz) from the velocity field's strain; zero on solid sites.
+hipError_t launch_strain(const uint32_t *links, const double *rho0, const double *rho1, const double *u, double tau0,
+                         double tau1, int nx, int ny, int nz, double *pi, hipStream_t s);
+// FP64 residual sums [sum d ra^2, sum ra^2, sum |d u|^2, sum |u|^2] as block
+// partials (nblocks blocks of 256 threads).
+hipError_t launch_residual(const double *ra, const double *u, const double *ra_prev, const double *u_prev, int64_t N,
+                           int nblocks, double *partials, hipStream_t s);
 // Internal state from ABI populations (inverse of the pull).
 hipError_t launch_set_pops(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *f, int nx,
                            int ny, int nz, int64_t ngroups, const double ref[2], hipStream_t s);

@@ -1506,10 +1506,77 @@ __device__ __forceinline__ double load_pop(const S *src, int64_t ngroups, int d,
 
 // The set-up and exchange kernels address a fluid site s's populations by
 // its slot idx[s] (solid sites have none).
+// The non-equilibrium part of component a's populations that a velocity
+// field's strain implies, for the warm start: f'_i = w_i / (2 T0^2)
+// (c_i c_i - T0 I) : Pi^a (the projection of Eq. 10) with the first-order
+// Chapman-Enskog flux of the mixture, Pi = -rho T0 tau_mix (grad u + grad u^T)
+// (tau_mix of Eqs. 5-6), shared by the components in proportion to their
+// densities, Pi^a = (rho_a / rho) Pi.  pi holds rho_a-independent
+// Pi / rho at each site, 6 values (xx, yy, zz, xy, xz, yz), component-major.
+__device__ __forceinline__ double neq_dir(int i, double rho_a, const double *pi, int64_t N, int64_t t) {
+    double out = 0.0;
+    sfor<19>([&](auto I) {
+        constexpr int j = I;
+        if (j == i) {
+            constexpr double T0 = 1.0 / 3.0;
+            constexpr double X = cx_of(j), Y = cy_of(j), Z = cz_of(j);
+            const double c = (X * X - T0) * pi[t] + (Y * Y - T0) * pi[N + t] + (Z * Z - T0) * pi[2 * N + t] +
+                             2.0 * (X * Y * pi[3 * N + t] + X * Z * pi[4 * N + t] + Y * Z * pi[5 * N + t]);
+            out = rho_a * w_of(j) / (2.0 * T0 * T0) * c;
+        }
+    });
+    return out;
+}
+
+// Pi / rho of the warm start at every fluid site (zero on solid sites): the
+// derivatives of u by three-point differences along each axis, a solid
+// neighbour standing for the wall half a site away with u = 0 (halfway
+// bounce-back); Pi / rho = -T0 tau_mix (grad u + grad u^T).
+__global__ void strain_kernel(const uint32_t *links, const double *rho0, const double *rho1, const double *u,
+                              double tau0, double tau1, int nx, int ny, int nz, double *pi) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t L = links[s];
+        double g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // g[d][b] = d u_b / d x_d
+        if (!(L & 1u)) {
+            int x, y, z;
+            site_coords(s, nx, ny, x, y, z);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                // link bit of the minus neighbour (site - e_d: direction +e_d) and of the plus one
+                const int bm = 2 * d + 1, bp = 2 * d + 2;
+                const int dx = d == 0, dy = d == 1, dz = d == 2;
+                const bool wm = (L >> bm) & 1u, wp = (L >> bp) & 1u;
+                const int64_t sm = site_shift(x, y, z, -dx, -dy, -dz, nx, ny, nz);
+                const int64_t sp = site_shift(x, y, z, dx, dy, dz, nx, ny, nz);
+                const double h1 = wm ? 0.5 : 1.0, h2 = wp ? 0.5 : 1.0;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const double v0 = u[b * N + s];
+                    const double v1 = wm ? 0.0 : u[b * N + sm], v2 = wp ? 0.0 : u[b * N + sp];
+                    g[d][b] = (h1 * h1 * v2 - h2 * h2 * v1 + (h2 * h2 - h1 * h1) * v0) / (h1 * h2 * (h1 + h2));
+                }
+            }
+        }
+        const double r0 = rho0[s], r1 = rho1[s], r = r0 + r1;
+        const double tau = (L & 1u) || !(r > 0) ? 0.0 : (r0 * tau0 + r1 * tau1) / r;
+        const double k = -(1.0 / 3.0) * tau;
+        pi[s] = k * 2.0 * g[0][0];
+        pi[N + s] = k * 2.0 * g[1][1];
+        pi[2 * N + s] = k * 2.0 * g[2][2];
+        pi[3 * N + s] = k * (g[0][1] + g[1][0]);
+        pi[4 * N + s] = k * (g[0][2] + g[2][0]);
+        pi[5 * N + s] = k * (g[1][2] + g[2][1]);
+    }
+}
+
+// Internal state from fields: f*_j(x) = f_j(x + c_j) if that site is fluid,
+// else f_opp(j)(x), with f = f_eq(rho_a, u) (Eq. 3), plus the strain's
+// non-equilibrium part when pi is given (warm start).
 template <typename S>
 __global__ void init_fields_kernel(S *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
-                                   const double *rho1, const double *u, int nx, int ny, int nz, int64_t ngroups,
-                                   int eq_kind, double ref0, double ref1) {
+                                   const double *rho1, const double *u, const double *pi, int nx, int ny, int nz,
+                                   int64_t ngroups, int eq_kind, double ref0, double ref1) {
     const int64_t N = (int64_t)nx * ny * nz;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t L = links[s];
@@ -1524,9 +1591,49 @@ __global__ void init_fields_kernel(S *dst, const uint32_t *links, const int32_t 
             const int64_t t = wall ? s : site_shift(x, y, z, cx_of(j), cy_of(j), cz_of(j), nx, ny, nz);
             const int kk = wall ? opp_of(j) : j;
             const double ux = u ? u[t] : 0.0, uy = u ? u[N + t] : 0.0, uz = u ? u[2 * N + t] : 0.0;
-            store_pop<S>(dst, ngroups, 0, j, k, feq_dir(kk, rho0[t], ux, uy, uz, eq_kind), ref0);
-            store_pop<S>(dst, ngroups, 1, j, k, feq_dir(kk, rho1[t], ux, uy, uz, eq_kind), ref1);
+            double f0 = feq_dir(kk, rho0[t], ux, uy, uz, eq_kind), f1 = feq_dir(kk, rho1[t], ux, uy, uz, eq_kind);
+            if (pi) {
+                f0 += neq_dir(kk, rho0[t], pi, N, t);
+                f1 += neq_dir(kk, rho1[t], pi, N, t);
+            }
+            store_pop<S>(dst, ngroups, 0, j, k, f0, ref0);
+            store_pop<S>(dst, ngroups, 1, j, k, f1, ref1);
         });
+    }
+}
+
+// FP64 sums of the convergence residual over all sites (solid sites hold 0
+// in both states): [sum (ra - ra_prev)^2, sum ra^2, sum |u - u_prev|^2,
+// sum |u|^2] per block into partials (kPartialStride per block).
+__global__ void residual_kernel(const double *ra, const double *u, const double *ra_prev, const double *u_prev,
+                                int64_t N, double *partials) {
+    __shared__ double red[4][4];
+    double acc[4] = {0, 0, 0, 0};
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
+        const double da = ra[s] - ra_prev[s];
+        acc[0] += da * da;
+        acc[1] += ra[s] * ra[s];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double v = u[d * N + s], dv = v - u_prev[d * N + s];
+            acc[2] += dv * dv;
+            acc[3] += v * v;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double v = acc[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[wv][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kPartialStride) {
+        double v = 0.0;
+        if (threadIdx.x < 4)
+            for (int q = 0; q < 4; ++q) v += red[q][threadIdx.x];
+        partials[(size_t)blockIdx.x * kPartialStride + threadIdx.x] = v;
     }
 }
 
@@ -1771,12 +1878,25 @@ hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, i
     }
 
 hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
-                              const double *rho1, const double *u, int nx, int ny, int nz, int64_t ngroups, int eq_kind,
-                              const double ref[2], hipStream_t s) {
+                              const double *rho1, const double *u, const double *pi, int nx, int ny, int nz,
+                              int64_t ngroups, int eq_kind, const double ref[2], hipStream_t s) {
     const int g = site_grid((int64_t)nx * ny * nz);
     LBM_DISPATCH_PREC(prec, S,
                       hipLaunchKernelGGL(init_fields_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<S *>(dst), links,
-                                         idx, rho0, rho1, u, nx, ny, nz, ngroups, eq_kind, ref[0], ref[1]));
+                                         idx, rho0, rho1, u, pi, nx, ny, nz, ngroups, eq_kind, ref[0], ref[1]));
+    return hipGetLastError();
+}
+
+hipError_t launch_strain(const uint32_t *links, const double *rho0, const double *rho1, const double *u, double tau0,
+                         double tau1, int nx, int ny, int nz, double *pi, hipStream_t s) {
+    hipLaunchKernelGGL(strain_kernel, dim3(site_grid((int64_t)nx * ny * nz)), dim3(256), 0, s, links, rho0, rho1, u,
+                       tau0, tau1, nx, ny, nz, pi);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const double *ra, const double *u, const double *ra_prev, const double *u_prev, int64_t N,
+                           int nblocks, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(residual_kernel, dim3(nblocks), dim3(256), 0, s, ra, u, ra_prev, u_prev, N, partials);
     return hipGetLastError();
 }
 

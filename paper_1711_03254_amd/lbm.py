@@ -28,7 +28,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_EMASSDRIFT = 0,
 ERROR_NAMES = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_ENONFINITE", -5: "LBM_EMASSDRIFT"}
 
 EXPORTED = ("lbm_init", "lbm_step", "lbm_moments", "lbm_reduce", "lbm_reduce_noalloc", "lbm_get_populations",
-            "lbm_set_populations", "lbm_set_fields", "lbm_info", "lbm_last_error", "lbm_free",
+            "lbm_set_populations", "lbm_set_fields", "lbm_set_fields_strain", "lbm_residual", "lbm_info", "lbm_last_error", "lbm_free",
             "lbm_batch_create", "lbm_batch_step", "lbm_batch_last_error", "lbm_batch_free")
 
 
@@ -94,6 +94,8 @@ def load_library():
     lib.lbm_get_populations.argtypes = [vp, vp, ctypes.c_int]
     lib.lbm_set_populations.argtypes = [vp, vp, ctypes.c_int]
     lib.lbm_set_fields.argtypes = [vp, vp, vp, vp, ctypes.c_int]
+    lib.lbm_set_fields_strain.argtypes = [vp, vp, vp, vp, ctypes.c_int]
+    lib.lbm_residual.argtypes = [vp, dp]
     lib.lbm_info.argtypes = [vp, ctypes.POINTER(lbm_info_t)]
     lib.lbm_last_error.argtypes = [vp]
     lib.lbm_last_error.restype = ctypes.c_char_p
@@ -282,18 +284,44 @@ def lbm_set_populations(ctx: Context, f) -> None:
     _check(ctx, load_library().lbm_set_populations(ctx.handle, p, d))
 
 
-def lbm_set_fields(ctx: Context, rho1, rho2, u=None) -> None:
-    ptrs, devs = [], set()
+def _field_args(rho1, rho2, u):
+    """Pointers and the common on_device flag of the field arrays; the
+    returned list keeps any contiguous copies alive for the call."""
+    ptrs, devs, keep = [], set(), []
     for a in (rho1, rho2, u):
         if isinstance(a, np.ndarray):
             a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
         p, d = _ptr(a)
         ptrs.append(p)
         if d is not None:
             devs.add(d)
     if len(devs) > 1:
         raise ValueError("inputs must be all on the host or all on the device")
-    _check(ctx, load_library().lbm_set_fields(ctx.handle, ptrs[0], ptrs[1], ptrs[2], devs.pop()))
+    return ptrs, devs.pop(), keep
+
+
+def lbm_set_fields(ctx: Context, rho1, rho2, u=None) -> None:
+    ptrs, dev, keep = _field_args(rho1, rho2, u)
+    _check(ctx, load_library().lbm_set_fields(ctx.handle, ptrs[0], ptrs[1], ptrs[2], dev))
+    del keep
+
+
+def lbm_set_fields_strain(ctx: Context, rho1, rho2, u) -> None:
+    """lbm_set_fields plus the non-equilibrium part of u's strain."""
+    if u is None:
+        raise LBMError(LBM_EINVAL, "lbm_set_fields_strain needs a velocity field")
+    ptrs, dev, keep = _field_args(rho1, rho2, u)
+    _check(ctx, load_library().lbm_set_fields_strain(ctx.handle, ptrs[0], ptrs[1], ptrs[2], dev))
+    del keep
+
+
+def lbm_residual(ctx: Context) -> tuple[float, float]:
+    """(relative change of u_F, relative change of rho1) since the previous
+    call, in FP64 on the device."""
+    out = np.zeros(2)
+    _check(ctx, load_library().lbm_residual(ctx.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return float(out[0]), float(out[1])
 
 
 def lbm_info(ctx: Context) -> dict:

@@ -34,26 +34,18 @@ def physics(g=1e-4, G=0.0, rho_s=0.0):
 
 
 class Residual:
-    """The residual above, from moments taken on the device every K steps."""
+    """The residual above, taken by the library in FP64 on the device
+    (lbm_residual) every K steps; the first sample only records the fields."""
 
-    def __init__(self, ctx, shape):
-        n = int(np.prod(shape))
-        self.ctx, self.n = ctx, n
-        self.ra = torch.zeros(n, dtype=torch.float64, device="cuda")
-        self.rb = torch.zeros(n, dtype=torch.float64, device="cuda")
-        self.u = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
-        self.prev = None
+    def __init__(self, ctx, shape=None):
+        self.ctx, self.first = ctx, True
 
     def sample(self):
-        lbm.lbm_moments(self.ctx, self.ra, self.rb, self.u)   # device outputs
-        cur = (self.ra.clone(), self.u.clone())
-        r = None
-        if self.prev is not None:
-            du = torch.linalg.vector_norm(cur[1] - self.prev[1]) / torch.linalg.vector_norm(cur[1]).clamp_min(1e-300)
-            da = torch.linalg.vector_norm(cur[0] - self.prev[0]) / torch.linalg.vector_norm(cur[0]).clamp_min(1e-300)
-            r = float(torch.maximum(du, da))
-        self.prev = cur
-        return r
+        du, da = lbm.lbm_residual(self.ctx)
+        if self.first:
+            self.first = False
+            return None
+        return max(du, da)
 
 
 def run_to_residual(ctx, shape, tol=1e-6, every=100, max_steps=100000):
@@ -168,8 +160,13 @@ def compare(net, sample, phys, tol, prec="fp32", every=100, max_steps=100000, de
                 prediction_rho_a_error=ea)
 
 
-def solve(solid, ra, rb, phys, u=None, tol=1e-6, every=100, max_steps=100000, prec="fp32"):
+def solve(solid, ra, rb, phys, u=None, tol=1e-6, every=100, max_steps=100000, prec="fp32", strain=False):
+    """One solve from the fields (ra, rb, u) to the residual tol.  With
+    strain, the initial populations also carry the non-equilibrium part of
+    u's strain (lbm_set_fields_strain), not the equilibrium alone."""
     ctx = make_context(solid, ra, rb, phys, prec, u)
+    if strain and u is not None:
+        lbm.lbm_set_fields_strain(ctx, ra, rb, u)
     t = time.perf_counter()
     steps, conv, hist = run_to_residual(ctx, solid.shape, tol, every, max_steps)
     torch.cuda.synchronize()

@@ -26,6 +26,111 @@ def record(name, **vals):
             fh.write(json.dumps({"test": name, **vals}) + "\n")
 
 
+def _channel(ny=34, nx=4, nz=4):
+    """A z-channel with walls at y = 0 and y = ny - 1 (the wall planes sit
+    half a site inside the fluid's first row, halfway bounce-back)."""
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[:, 0, :] = 1
+    solid[:, ny - 1, :] = 1
+    return solid
+
+
+D3Q19 = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                  [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1], [1, 0, -1], [-1, 0, 1],
+                  [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]])
+
+
+def test_strain_start_sets_the_viscous_flux():
+    """lbm_set_fields_strain on a parabolic channel profile: the shear moment
+    sum_i c_y c_z f_i of each component must equal its density share of the
+    Chapman-Enskog flux -rho T0 tau_mix du_z/dy exactly (three-point
+    differences are exact on a parabola, also at the half-site walls), while
+    the mass and momentum moments stay those of the fields."""
+    from paper_1711_03254_amd import lbm
+    lbm.load_library()
+    ny = 34
+    solid = _channel(ny)
+    y = np.arange(ny, dtype=np.float64)
+    prof = 4e-3 * (y - 0.5) * (ny - 1.5 - y)
+    ra = np.where(solid == 1, 0.0, 0.7)
+    rb = np.where(solid == 1, 0.0, 0.3)
+    u = np.zeros((3,) + solid.shape)
+    u[2] = np.where(solid == 1, 0.0, prof[None, :, None])
+    tau = (0.8, 1.3)
+    ctx = lbm.lbm_init(lbm.Params(4, ny, 4, prec=lbm.LBM_FP64, tau=tau, solid=solid, rho_init=(ra, rb), u_init=u))
+    lbm.lbm_set_fields_strain(ctx, ra, rb, u)
+    f = lbm.lbm_get_populations(ctx)
+    c = D3Q19.astype(np.float64)
+    fl = solid == 0
+    tmix = (0.7 * tau[0] + 0.3 * tau[1]) / 1.0
+    dudy = 4e-3 * (ny - 1.5 - y - (y - 0.5))
+    want = -(1.0 / 3.0) * tmix * dudy[None, :, None] * np.ones(solid.shape)
+    for a, share in ((0, 0.7), (1, 0.3)):
+        pyz = np.einsum("i,i...->...", c[:, 1] * c[:, 2], f[a])
+        np.testing.assert_allclose(pyz[fl], (share * want)[fl], rtol=1e-12, atol=1e-16)
+        mass = f[a].sum(0)
+        np.testing.assert_allclose(mass[fl], share, rtol=1e-13)
+        jz = np.einsum("i,i...->...", c[:, 2], f[a])
+        np.testing.assert_allclose(jz[fl], (share * u[2])[fl], rtol=1e-12, atol=1e-17)
+    lbm.lbm_free(ctx)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_strain_start_is_near_steady(prec):
+    """A miscible mixture in a body-force-driven channel started from its
+    steady Poiseuille profile: with the strain's non-equilibrium part the
+    first steps barely change u (the viscous stress already balances the
+    force); from the equilibrium alone the force accelerates the fluid
+    unopposed until the stress has built up.  tau_mix = 0.61: at tau_mix = 1
+    the collision discards the non-equilibrium part whatever it is, and
+    the two starts coincide after one step.  The profile given is the bare
+    velocity sum c f / rho = u_F - g / 2 of the steady state."""
+    from paper_1711_03254_amd import lbm
+    lbm.load_library()
+    ny = 34
+    solid = _channel(ny)
+    y = np.arange(ny, dtype=np.float64)
+    tau = (0.55, 0.7)
+    phi = 0.6
+    nu = (1.0 / 3.0) * ((phi * tau[0] + (1 - phi) * tau[1]) - 0.5)
+    g = 1e-6
+    prof = g / (2 * nu) * (y - 0.5) * (ny - 1.5 - y)
+    ra = np.where(solid == 1, 0.0, phi)
+    rb = np.where(solid == 1, 0.0, 1 - phi)
+    u = np.zeros((3,) + solid.shape)
+    u[2] = np.where(solid == 1, 0.0, prof[None, :, None] - g / 2)
+    change = {}
+    for strain in (False, True):
+        ctx = lbm.lbm_init(lbm.Params(4, ny, 4, prec=lbm.PRECISIONS[prec], tau=tau, g=(0.0, 0.0, g), solid=solid,
+                                      rho_init=(ra, rb), u_init=u))
+        if strain:
+            lbm.lbm_set_fields_strain(ctx, ra, rb, u)
+        lbm.lbm_residual(ctx)
+        lbm.lbm_step(ctx, 10)
+        change[strain] = lbm.lbm_residual(ctx)[0]
+        lbm.lbm_free(ctx)
+    record(f"strain_start_{prec}", eq_change=change[False], strain_change=change[True])
+    assert change[True] < 0.2 * change[False]
+
+
+def test_residual_matches_the_fields():
+    """lbm_residual against the same norms taken on the host from
+    lbm_moments, on a coupled mixture in a porous subvolume."""
+    from paper_1711_03254_amd import inputs, lbm, warmstart as ws
+    lbm.load_library()
+    solid, ra0, rb0, _ = inputs.mixture_case(32, 901, radius_range=(1.5, 4.0))
+    ctx = ws.make_context(solid, ra0, rb0, ws.physics(G=-1.0), "fp64")
+    assert lbm.lbm_residual(ctx) == (1.0, 1.0)    # against zero fields
+    a0, _, u0 = lbm.lbm_moments(ctx)
+    lbm.lbm_step(ctx, 7)
+    du, da = lbm.lbm_residual(ctx)
+    a1, _, u1 = lbm.lbm_moments(ctx)
+    np.testing.assert_allclose(du, np.linalg.norm(u1 - u0) / np.linalg.norm(u1), rtol=1e-10)
+    np.testing.assert_allclose(da, np.linalg.norm(a1 - a0) / np.linalg.norm(a1), rtol=1e-10)
+    assert lbm.lbm_residual(ctx) == (0.0, 0.0)    # nothing stepped since the last call
+    lbm.lbm_free(ctx)
+
+
 def test_warm_start_end_to_end():
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
