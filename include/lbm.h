@@ -96,7 +96,8 @@ typedef struct {
                                     1: each component gives up its density share of the mixture's
                                     net wall force, so that the walls separate the components
                                     without pushing the mixture (W2, the momentum-balanced wall
-                                    interaction of Section 3.3) */
+                                    interaction of Section 2 after Eq. 11, used in
+                                    Section 3.5) */
     double tau_crit;             /* FP32 and 16-bit storage: sites whose mixture relaxation time
                                     (Eqs. 5-6) is below tau_crit accumulate the second moments of
                                     the collision (the non-equilibrium flux of Eq. 10) in FP64:
@@ -163,14 +164,17 @@ int lbm_set_populations(lbm_ctx *c, const double *f, int on_device);
  * u may be NULL (rest).  Component masses for the check are re-recorded. */
 int lbm_set_fields(lbm_ctx *c, const double *rho1, const double *rho2, const double *u, int on_device);
 
-/* Warm start with a non-equilibrium part: as lbm_set_fields, plus the part
- * of the populations that the strain of u implies to first order in the
- * Chapman-Enskog expansion (the moment behind the regularization of
- * Eq. 10): Pi = -rho T0 tau_mix (grad u + grad u^T) with tau_mix of
- * Eqs. (5-6), shared by the components in proportion to their densities
- * and projected as in Eq. (10).  grad u takes central differences, with a
- * solid neighbour standing for a wall half a site away where u = 0.
- * u (3N) is required.  Allocates and frees a 6N-double work buffer.
+/* Restart from macroscopic fields, as lbm_moments reports them: rho1, rho2
+ * and the force-shifted velocity u_F of Eq. (8) (3N, required).  Component
+ * a's populations are f_eq(rho_a, u_F - F_a / (2 rho_a)) (Eq. 3, with F_a
+ * the force of Eqs. 7 and 11 plus rho_a g evaluated on the given densities,
+ * so that Eq. 8 gives back u_F) plus the non-equilibrium part that the
+ * strain of u_F implies to first order in the Chapman-Enskog expansion:
+ * Pi = -rho T0 tau_mix (grad u_F + grad u_F^T) (tau_mix of Eqs. 5-6),
+ * shared by the components in proportion to their densities and projected
+ * as in Eq. (10).  grad u_F takes central differences, a solid neighbour
+ * standing for a wall half a site away where u_F = 0.  Component masses for
+ * the check are re-recorded.  Allocates and frees a 12N-double work buffer.
  * Errors: LBM_EINVAL (NULL argument or invalid fields), LBM_ENOMEM,
  * LBM_EDEVICE. */
 int lbm_set_fields_strain(lbm_ctx *c, const double *rho1, const double *rho2, const double *u, int on_device);
@@ -185,6 +189,16 @@ int lbm_set_fields_strain(lbm_ctx *c, const double *rho1, const double *rho2, co
  * with a zero difference gives 0.  Synchronizes the context's stream.
  * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE. */
 int lbm_residual(lbm_ctx *c, double out[2]);
+
+/* Distance of the current state from given fields, in FP64 on the device:
+ * out[0] = ||u_F - u|| / ||u||, out[1] = ||rho1 - r1|| / ||r1|| (2-norms over
+ * the lattice; u_F of Eq. 8, as lbm_moments reports it), for judging a solve
+ * against a reference state.  r1 (N) and u (3N) are host arrays or, with
+ * on_device, device arrays; host arrays are staged through a temporary 4N-
+ * double device buffer.  Does not touch the residual's fields.  A zero norm
+ * with a zero difference gives 0.  Synchronizes the context's stream.
+ * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE. */
+int lbm_distance(lbm_ctx *c, const double *r1, const double *u, int on_device, double out[2]);
 
 /* Facts about a context, for reports: number of fluid sites, steps done,
  * bytes of population storage per site update (read + write), and the

@@ -95,6 +95,33 @@ int nn_adam(float *param, const float *grad, float *m, float *v, uint16_t *param
 /* y = bf16(x), n elements (contiguous). */
 int nn_to_bf16(const float *x, uint16_t *y, int64_t n, void *stream);
 
+/* The surrogate's geometry feature: Euclidean distance (FP32) from each of
+ * the d x h x w sites of a periodic lattice (x fastest) to the nearest site
+ * with solid[s] != 0, exact wherever that site lies within +-radius along
+ * every axis, else radius sqrt(3).  Separable: the distance along x, then
+ * minima over y and z of the squared distances.  work: FP32 scratch of 2
+ * d h w floats. */
+int nn_solid_distance(const uint8_t *solid, float *work, float *dist, int32_t d, int32_t h, int32_t w_, int32_t radius,
+                      void *stream);
+
+/* The surrogate's input: bf16 channels [solid, rho_a / (rho_a + rho_b) on
+ * fluid sites (else 0), dist / dist_scale, 0, ...] for p positions, c >= 3
+ * channels at stride ldx >= c. */
+int nn_features(const uint8_t *solid, const double *rho_a, const double *rho_b, const float *dist, float dist_scale,
+                uint16_t *x, int32_t ldx, int32_t c, int64_t p, void *stream);
+
+/* The warm state from the surrogate's output (FP32 view out, ldo >= 5:
+ * [ux, uy, uz, d rho_a, d rho_b] in units of u_scale g / nu_mix and
+ * rho_scale), at fluid sites: u = out * u_scale * g / nu_mix with nu_mix =
+ * phi nu_a + (1 - phi) nu_b of the initial fraction phi (Eqs. 5-6), rho =
+ * max(rho0 + rho_scale * out, floor), then each density rescaled so that
+ * its sum over fluid sites equals that of rho0 (FP64 sums in a fixed
+ * order); zero on solid sites.  u: 3p doubles (component-major), rho_a,
+ * rho_b: p doubles; work: FP64 scratch of at least 4096 doubles. */
+int nn_decode_fields(const float *out, int32_t ldo, const uint8_t *solid, const double *rho_a0, const double *rho_b0,
+                     double nu_a, double nu_b, double g, float u_scale, float rho_scale, double floor, double *u,
+                     double *rho_a, double *rho_b, double *work, int64_t p, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

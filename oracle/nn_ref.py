@@ -15,8 +15,9 @@ float64 with NumPy, on channel-last arrays x[b, z, y, x, c]:
 * its two adjoints (gradient with respect to the input and to the weights);
 * ReLU, 2 x 2 x 2 average pooling, nearest 2x upsampling, channel concat;
 * the weighted mean-square loss;
-* the encoder-decoder built from them (UNet below) with its forward and
-  backward passes.
+* the encoder-decoder built from them (levels of two convolutions, 2x
+  average pooling down, nearest upsampling and concatenation with the
+  level's encoder output up) with its forward and backward passes.
 
 Pinned by tests/test_nn_oracle.py: a brute-force loop convolution, the
 adjoint identities <A x, y> = <x, A^T y>, and central finite differences of
@@ -92,19 +93,31 @@ def mse(pred, target, cw):
 
 
 # ---------------------------------------------------------------------------
-# The encoder-decoder.  Layer list: (name, ci, co, relu); the skip
-# connections concatenate [upsampled, encoder] channels.
+# The encoder-decoder.  Layer list: (name, ci, co, relu).  Level k = 1..L
+# of the encoder works at 1/2^(k-1) resolution with widths base * k; the
+# bottleneck (b1, b2) at 1/2^L keeps the last width; decoder layer dk
+# takes [upsampled, encoder level k output] channels at level k.
 # ---------------------------------------------------------------------------
-def layers(cin, cout, base):
-    c1, c2 = base, 2 * base
-    return [
-        ("e1a", cin, c1, True), ("e1b", c1, c1, True),      # full resolution
-        ("e2a", c1, c2, True), ("e2b", c2, c2, True),       # 1/2
-        ("b1", c2, c2, True), ("b2", c2, c2, True),         # 1/4
-        ("d2", 2 * c2, c2, True),                           # 1/2: [up(b2), e2b]
-        ("d1", c2 + c1, c1, True),                          # full: [up(d2), e1b]
-        ("out", c1, cout, False),
-    ]
+def widths(base, levels):
+    return [base * (k + 1) for k in range(levels)]
+
+
+def layers(cin, cout, base, levels=3):
+    ch = widths(base, levels)
+    spec = []
+    for k in range(levels):
+        spec += [(f"e{k + 1}a", cin if k == 0 else ch[k - 1], ch[k], True), (f"e{k + 1}b", ch[k], ch[k], True)]
+    spec += [("b1", ch[-1], ch[-1], True), ("b2", ch[-1], ch[-1], True)]
+    up = ch[-1]
+    for k in range(levels, 0, -1):
+        spec.append((f"d{k}", up + ch[k - 1], ch[k - 1], True))
+        up = ch[k - 1]
+    spec.append(("out", ch[0], cout, False))
+    return spec
+
+
+def levels_of(spec):
+    return sum(1 for l in spec if l[0].startswith("e") and l[0].endswith("a"))
 
 
 def _same(a):
@@ -116,27 +129,29 @@ def forward(params, x, spec, store=_same):
     store(a) is applied to every stored activation (identity by default; a
     caller that emulates reduced-precision storage passes its rounding).
     The output layer's result is not passed through store."""
+    L = levels_of(spec)
     spec = {l[0]: l for l in spec}
     a = {}
+
     def conv(name, inp):
         w, b = params[name]
         y = conv3d(inp, w, b)
         y = relu(y) if spec[name][3] else y
         return y if name == "out" else store(y)
-    a["x"] = x
-    a["e1a"] = conv("e1a", x)
-    a["e1b"] = conv("e1b", a["e1a"])
-    a["p1"] = store(pool2(a["e1b"]))
-    a["e2a"] = conv("e2a", a["p1"])
-    a["e2b"] = conv("e2b", a["e2a"])
-    a["p2"] = store(pool2(a["e2b"]))
-    a["b1"] = conv("b1", a["p2"])
-    a["b2"] = conv("b2", a["b1"])
-    a["c2"] = np.concatenate([up2(a["b2"]), a["e2b"]], axis=-1)
-    a["d2"] = conv("d2", a["c2"])
-    a["c1"] = np.concatenate([up2(a["d2"]), a["e1b"]], axis=-1)
-    a["d1"] = conv("d1", a["c1"])
-    a["out"] = conv("out", a["d1"])
+
+    a["x"] = h = x
+    for k in range(1, L + 1):
+        if k > 1:
+            h = a[f"p{k - 1}"] = store(pool2(a[f"e{k - 1}b"]))
+        a[f"e{k}a"] = conv(f"e{k}a", h)
+        a[f"e{k}b"] = conv(f"e{k}b", a[f"e{k}a"])
+    a[f"p{L}"] = store(pool2(a[f"e{L}b"]))
+    a["b1"] = conv("b1", a[f"p{L}"])
+    h = a["b2"] = conv("b2", a["b1"])
+    for k in range(L, 0, -1):
+        a[f"c{k}"] = np.concatenate([up2(h), a[f"e{k}b"]], axis=-1)
+        h = a[f"d{k}"] = conv(f"d{k}", a[f"c{k}"])
+    a["out"] = conv("out", h)
     return a["out"], a
 
 
@@ -145,8 +160,10 @@ def backward(params, a, dout, spec, store=_same):
     the output is dout, and the gradient with respect to the input.
     store(g) is applied to the gradient at each convolution's output (after
     the ReLU mask) before both of its uses."""
+    L = levels_of(spec)
     spec = {l[0]: l for l in spec}
     g = {}
+
     def conv_back(name, inp, dy):
         w, _ = params[name]
         if spec[name][3]:
@@ -154,24 +171,22 @@ def backward(params, a, dout, spec, store=_same):
         dy = store(dy)
         g[name] = conv3d_bwd_weight(inp, dy)
         return conv3d_bwd_data(dy, w)
-    dd1 = conv_back("out", a["d1"], dout)
-    dc1 = conv_back("d1", a["c1"], dd1)
-    c_up = a["d2"].shape[-1]
-    dd2 = up2_bwd(dc1[..., :c_up])
-    de1b = dc1[..., c_up:].copy()
-    dc2 = conv_back("d2", a["c2"], dd2)
-    c_up2 = a["b2"].shape[-1]
-    db2 = up2_bwd(dc2[..., :c_up2])
-    de2b = dc2[..., c_up2:].copy()
-    db1 = conv_back("b2", a["b1"], db2)
-    dp2 = conv_back("b1", a["p2"], db1)
-    de2b += pool2_bwd(dp2)
-    de2a = conv_back("e2b", a["e2a"], de2b)
-    dp1 = conv_back("e2a", a["p1"], de2a)
-    de1b += pool2_bwd(dp1)
-    de1a = conv_back("e1b", a["e1a"], de1b)
-    dx = conv_back("e1a", a["x"], de1a)
-    return g, dx
+
+    dh = conv_back("out", a["d1"], dout)
+    de = {}
+    for k in range(1, L + 1):
+        dc = conv_back(f"d{k}", a[f"c{k}"], dh)
+        below = a[f"d{k + 1}"] if k < L else a["b2"]
+        c_up = below.shape[-1]
+        dh = up2_bwd(dc[..., :c_up])
+        de[k] = dc[..., c_up:].copy()
+    db1 = conv_back("b2", a["b1"], dh)
+    dp = conv_back("b1", a[f"p{L}"], db1)
+    for k in range(L, 0, -1):
+        de[k] += pool2_bwd(dp)
+        dea = conv_back(f"e{k}b", a[f"e{k}a"], de[k])
+        dp = conv_back(f"e{k}a", a[f"p{k - 1}"] if k > 1 else a["x"], dea)
+    return g, dp
 
 
 def init_params(spec, seed):

@@ -1,6 +1,6 @@
 """Critical pressure for pushing a wetting slug out of a constriction, Eq. (12).
 
-Section 3.4 sets a slug of the second component over the junction of a
+Section 3.6 sets a slug of the second component over the junction of a
 narrow channel (height D) and a wide one (height H > D) in a periodic
 two-dimensional channel of length L, with walls that the slug wets
 (contact angle theta <= 90 degrees measured inside the second component).
@@ -108,7 +108,7 @@ def slug_position(rb, solid, minor=0.03):
 
 def ramp(sigma, theta_deg, D=10, H=40, L=160, Z=52, rho_s=0.4, G=-4.2, tau=(1.0, 1.0), steps=80000,
          stages=STAGES, prec="fp32", slug=(78, 109), x0=54, wall_kind=0):
-    """Runs the staged drive of Section 3.4 and reports, per stage, where
+    """Runs the staged drive of Section 3.6 and reports, per stage, where
     the slug's centre is (unwrapped along x) and how far it moved.  The slug
     (400 sites of the second component, 40 sites long inside the narrow
     part) starts over the exit of the narrow part at x0 + Z; the drive
@@ -154,3 +154,38 @@ def transition(result):
             return prev, row["stage"]
         prev = row["stage"]
     return prev, None
+
+
+def sweep(nus=((0.0017, 0.33), (0.33, 0.0017)), rho_s_values=(0.3, 0.5, 0.7), heights=(5, 10), G=-4.2,
+          log=None):
+    """The grid of Section 3.6 on the solver: per viscosity pair (nu_1, nu_2)
+    (component 2 is the slug) and wall parameter, the contact angle inside
+    the slug from the calibration at those viscosities, then the staged
+    drive at each narrow height D.  sigma is measured once at tau = 1 (it
+    does not depend on the viscosities).  Returns one row per case with
+    the transition band (None where the run turned non-finite: the slug's
+    position is then NaN)."""
+    from . import contact_angle as ca
+    sigma, _, _ = surface_tension(G=G, tau=1.0)
+    rows = []
+    for nu in nus:
+        tau = (nu[0] / T0 + 0.5, nu[1] / T0 + 0.5)
+        for rho_s in rho_s_values:
+            theta2 = 180.0 - ca.measure(rho_s, G=G, tau=tau, steps=20000)["theta_deg"]
+            for D in heights:
+                r = ramp(sigma, theta2, D=D, rho_s=rho_s, G=G, tau=tau)
+                finite = all(np.isfinite(s["slug_x"]) for s in r["stages"])
+                row = {"nu": list(nu), "rho_s": rho_s, "theta2": theta2, "D": D, "g_crit": r["g_crit"],
+                       "finite": finite, "transition": transition(r) if finite else None,
+                       "slug_x": {s["stage"]: s["slug_x"] for s in r["stages"]}, "exit_x": r["exit_x"]}
+                rows.append(row)
+                if log:
+                    log(row)
+    return {"sigma": sigma, "rows": rows}
+
+
+if __name__ == "__main__":
+    import json
+    lbm.load_library()
+    res = sweep(log=lambda row: print(json.dumps(row), flush=True))
+    print(json.dumps({"sigma": res["sigma"]}), flush=True)

@@ -297,25 +297,31 @@ int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u,
     HIPCHK(c, hipMemcpyAsync(c->stage, vr0, NB, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->stage + c->N, vr1, NB, hipMemcpyHostToDevice, c->stream));
     if (vu) HIPCHK(c, hipMemcpyAsync(c->stage + 2 * c->N, vu, 3 * NB, hipMemcpyHostToDevice, c->stream));
-    double *pi = nullptr;
+    // Warm start from u_F: the strain's flux Pi / rho (6N) and each
+    // component's force per unit density (6N) in one work buffer.
+    double *work = nullptr, *pi = nullptr, *acc = nullptr;
+    hipError_t e = hipSuccess;
     if (strain && vu) {
-        if (hipMalloc(&pi, 6 * NB) != hipSuccess) {
+        if (hipMalloc(&work, 12 * NB) != hipSuccess) {
             (void)hipGetLastError();
-            return fail(c, LBM_ENOMEM, "cannot allocate the 6N-double strain buffer");
+            return fail(c, LBM_ENOMEM, "cannot allocate the 12N-double warm-start buffer");
         }
-        hipError_t e = lbm::launch_strain(c->links, c->stage, c->stage + c->N, c->stage + 2 * c->N, c->p.tau[0],
-                                          c->p.tau[1], c->p.nx, c->p.ny, c->p.nz, pi, c->stream);
-        if (e != hipSuccess) {
-            (void)hipFree(pi);
-            return fail(c, LBM_EDEVICE, std::string("strain: ") + hipGetErrorString(e));
-        }
+        pi = work;
+        acc = work + 6 * c->N;
+        const double wall0 = c->p.rho_s < 0 ? -c->p.rho_s : 0.0, wall1 = c->p.rho_s > 0 ? c->p.rho_s : 0.0;
+        e = lbm::launch_strain(c->links, c->stage, c->stage + c->N, c->stage + 2 * c->N, c->p.tau[0], c->p.tau[1],
+                               c->p.nx, c->p.ny, c->p.nz, pi, c->stream);
+        if (e == hipSuccess)
+            e = lbm::launch_accel(c->links, c->stage, c->stage + c->N, c->p.G, wall0, wall1, c->p.wall_kind, c->p.g,
+                                  c->p.nx, c->p.ny, c->p.nz, acc, c->stream);
     }
-    hipError_t e = lbm::launch_init_fields(c->p.prec, c->f[c->cur], c->links, c->idx, c->stage, c->stage + c->N,
-                                           vu ? c->stage + 2 * c->N : nullptr, pi, c->p.nx, c->p.ny, c->p.nz,
-                                           c->ngroups, c->p.eq_kind, c->ref, c->stream);
-    if (pi) {
+    if (e == hipSuccess)
+        e = lbm::launch_init_fields(c->p.prec, c->f[c->cur], c->links, c->idx, c->stage, c->stage + c->N,
+                                    vu ? c->stage + 2 * c->N : nullptr, pi, acc, c->p.nx, c->p.ny, c->p.nz,
+                                    c->ngroups, c->p.eq_kind, c->ref, c->stream);
+    if (work) {
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        (void)hipFree(pi);
+        (void)hipFree(work);
     }
     if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("init_fields: ") + hipGetErrorString(e));
     c->snap_valid = false;
@@ -812,6 +818,35 @@ int lbm_set_fields_strain(lbm_ctx *c, const double *rho1, const double *rho2, co
     return load_fields(c, rho1, rho2, u, on_device, true);
 }
 
+namespace {
+
+// Distance sums of the current state (rho1, u_F) against (ra_prev, u_prev)
+// (device, N and 3N) into c->red_host; the current fields are left in the
+// staging buffer (rho1 at [0, N), u_F at [2N, 5N)).
+int distance_sums(lbm_ctx *c, const double *ra_prev, const double *u_prev) {
+    const size_t NB = sizeof(double) * (size_t)c->N;
+    double *ra = c->stage, *u = c->stage + 2 * c->N;
+    HIPCHK(c, hipMemsetAsync(ra, 0, NB, c->stream));
+    HIPCHK(c, hipMemsetAsync(u, 0, 3 * NB, c->stream));
+    lbm::StepLaunch L = make_launch(c, c->f[c->cur], nullptr);
+    L.out_rho0 = ra;
+    L.out_u = u;
+    HIPCHK(c, lbm::launch_step(c->p.prec, lbm::MODE_MOMENTS, L, c->stream));
+    const int nb = std::min<int64_t>(nblocks(c), std::max<int64_t>(1, (c->N + 255) / 256));
+    HIPCHK(c, lbm::launch_residual(ra, u, ra_prev, u_prev, c->N, nb, c->partials, c->stream));
+    HIPCHK(c, lbm::launch_finalize(c->partials, nb, c->red_dev, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->red_host, c->red_dev, sizeof(double) * lbm::kPartialStride, hipMemcpyDeviceToHost,
+                             c->stream));
+    return LBM_OK;
+}
+
+double rel_norm(double diff2, double norm2) {
+    if (norm2 > 0) return std::sqrt(diff2 / norm2);
+    return diff2 > 0 ? HUGE_VAL : 0.0;
+}
+
+}  // namespace
+
 int lbm_residual(lbm_ctx *c, double out[2]) {
     if (!c || !out) return fail(c, LBM_EINVAL, "lbm_residual: NULL argument");
     HIPCHK(c, hipSetDevice(c->device));
@@ -827,31 +862,50 @@ int lbm_residual(lbm_ctx *c, double out[2]) {
         c->snap_valid = false;
     }
     if (!c->snap_valid) HIPCHK(c, hipMemsetAsync(c->snap, 0, 4 * NB, c->stream));
-    // rho1 at stage[0, N), u_F at stage[2N, 5N); solid sites stay 0.
-    double *ra = c->stage, *u = c->stage + 2 * c->N;
-    HIPCHK(c, hipMemsetAsync(ra, 0, NB, c->stream));
-    HIPCHK(c, hipMemsetAsync(u, 0, 3 * NB, c->stream));
-    lbm::StepLaunch L = make_launch(c, c->f[c->cur], nullptr);
-    L.out_rho0 = ra;
-    L.out_u = u;
-    HIPCHK(c, lbm::launch_step(c->p.prec, lbm::MODE_MOMENTS, L, c->stream));
-    const int nb = std::min<int64_t>(nblocks(c), std::max<int64_t>(1, (c->N + 255) / 256));
-    HIPCHK(c, lbm::launch_residual(ra, u, c->snap, c->snap + c->N, c->N, nb, c->partials, c->stream));
-    HIPCHK(c, lbm::launch_finalize(c->partials, nb, c->red_dev, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->red_host, c->red_dev, sizeof(double) * lbm::kPartialStride, hipMemcpyDeviceToHost,
-                             c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->snap, ra, NB, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->snap + c->N, u, 3 * NB, hipMemcpyDeviceToDevice, c->stream));
+    rc = distance_sums(c, c->snap, c->snap + c->N);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->snap, c->stage, NB, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->snap + c->N, c->stage + 2 * c->N, 3 * NB, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->snap_valid = true;
-    auto rel = [](double diff2, double norm2) {
-        if (norm2 > 0) return std::sqrt(diff2 / norm2);
-        return diff2 > 0 ? HUGE_VAL : 0.0;
-    };
-    out[0] = rel(c->red_host[2], c->red_host[3]);
-    out[1] = rel(c->red_host[0], c->red_host[1]);
-    if (!std::isfinite(c->red_host[0] + c->red_host[1] + c->red_host[2] + c->red_host[3]))
-        return fail(c, LBM_ENONFINITE, "lbm_residual: non-finite fields");
+    const double *r = c->red_host;
+    if (!std::isfinite(r[0] + r[1] + r[2] + r[3])) return fail(c, LBM_ENONFINITE, "lbm_residual: non-finite fields");
+    out[0] = rel_norm(r[2], r[3]);
+    out[1] = rel_norm(r[0], r[1]);
+    return LBM_OK;
+}
+
+int lbm_distance(lbm_ctx *c, const double *rho1, const double *u, int on_device, double out[2]) {
+    if (!c || !rho1 || !u || !out) return fail(c, LBM_EINVAL, "lbm_distance: NULL argument");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = ensure_stage(c);
+    if (rc) return rc;
+    const size_t NB = sizeof(double) * (size_t)c->N;
+    double *tmp = nullptr;
+    const double *ra_ref = rho1, *u_ref = u;
+    if (!on_device) {
+        if (hipMalloc(&tmp, 4 * NB) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, LBM_ENOMEM, "lbm_distance: cannot allocate the 4N-double staging buffer");
+        }
+        if (hipMemcpyAsync(tmp, rho1, NB, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(tmp + c->N, u, 3 * NB, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+            (void)hipStreamSynchronize(c->stream);
+            (void)hipFree(tmp);
+            return fail(c, LBM_EDEVICE, "lbm_distance: copy failed");
+        }
+        ra_ref = tmp;
+        u_ref = tmp + c->N;
+    }
+    rc = distance_sums(c, ra_ref, u_ref);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("lbm_distance: ") + hipGetErrorString(e));
+    const double *r = c->red_host;
+    if (!std::isfinite(r[0] + r[2] + r[4] + r[5])) return fail(c, LBM_ENONFINITE, "lbm_distance: non-finite fields");
+    out[0] = rel_norm(r[2], r[5]);
+    out[1] = rel_norm(r[0], r[4]);
     return LBM_OK;
 }
 

@@ -62,17 +62,24 @@ hipError_t launch_finalize(const double *partials, int nblocks, double *out, hip
 hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, int nz, hipStream_t s);
 // Internal state from fields: f*_j(x) = f_j(x + c_j) if that site is fluid,
 // else f_opp(j)(x), with f = f_eq from rho (2N), u (3N or null), plus the
-// strain's non-equilibrium part when pi (6N, launch_strain) is given.
+// strain's non-equilibrium part when pi (6N, launch_strain) is given; with
+// acc (6N, launch_accel) u is u_F and component a takes u_F - acc_a / 2.
 // Populations of fluid site s are at slot idx[s].
 hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
-                              const double *rho1, const double *u, const double *pi, int nx, int ny, int nz,
-                              int64_t ngroups, int eq_kind, const double ref[2], hipStream_t s);
+                              const double *rho1, const double *u, const double *pi, const double *acc, int nx,
+                              int ny, int nz, int64_t ngroups, int eq_kind, const double ref[2], hipStream_t s);
+// F_a / rho_a of each component (6N) from the densities: Eqs. (7) and (11)
+// with the wall densities wall0, wall1 (W2 when wall_kind is 1), plus g.
+hipError_t launch_accel(const uint32_t *links, const double *rho0, const double *rho1, double G, double wall0,
+                        double wall1, int wall_kind, const double g[3], int nx, int ny, int nz, double *acc,
+                        hipStream_t s);
 // Pi / rho of the warm start's non-equilibrium part (6N: xx, yy, zz, xy, xz,
 // yz) from the velocity field's strain; zero on solid sites.
 hipError_t launch_strain(const uint32_t *links, const double *rho0, const double *rho1, const double *u, double tau0,
                          double tau1, int nx, int ny, int nz, double *pi, hipStream_t s);
-// FP64 residual sums [sum d ra^2, sum ra^2, sum |d u|^2, sum |u|^2] as block
-// partials (nblocks blocks of 256 threads).
+// FP64 distance sums [sum d ra^2, sum ra^2, sum |d u|^2, sum |u|^2,
+// sum ra_prev^2, sum |u_prev|^2] as block partials (nblocks blocks of 256
+// threads).
 hipError_t launch_residual(const double *ra, const double *u, const double *ra_prev, const double *u_prev, int64_t N,
                            int nblocks, double *partials, hipStream_t s);
 // Internal state from ABI populations (inverse of the pull).

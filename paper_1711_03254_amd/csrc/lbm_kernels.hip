@@ -1570,13 +1570,70 @@ __global__ void strain_kernel(const uint32_t *links, const double *rho0, const d
     }
 }
 
+// Force per unit density of each component at the fluid sites, F_a / rho_a
+// (acc, 6N: component-major, then x, y, z): the Shan-Chen part of Eq. (7)
+// with psi = rho, the wall part of Eq. (11) from the wall densities of solid
+// neighbours (W2: less the component's density share of the mixture's net
+// wall force), and the body acceleration g.  Zero on solid sites.
+__global__ void accel_kernel(const uint32_t *links, const double *rho0, const double *rho1, double G, double wall0,
+                             double wall1, int wall_kind, double gx, double gy, double gz, int nx, int ny, int nz,
+                             double *acc) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t L = links[s];
+        double ff[2][3] = {{0, 0, 0}, {0, 0, 0}}, fw[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        double a[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        if (!(L & 1u)) {
+            int x, y, z;
+            site_coords(s, nx, ny, x, y, z);
+            sfor<19>([&](auto I) {
+                constexpr int i = I;
+                if constexpr (i > 0) {
+                    constexpr double W = w_of(i), X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
+                    if ((L >> opp_of(i)) & 1u) {   // x + c_i is solid: component a sees the other's wall density
+                        fw[0][0] += W * X * wall1; fw[0][1] += W * Y * wall1; fw[0][2] += W * Z * wall1;
+                        fw[1][0] += W * X * wall0; fw[1][1] += W * Y * wall0; fw[1][2] += W * Z * wall0;
+                    } else {
+                        const int64_t t = site_shift(x, y, z, cx_of(i), cy_of(i), cz_of(i), nx, ny, nz);
+                        const double p0 = rho0[t], p1 = rho1[t];
+                        ff[0][0] += W * X * p1; ff[0][1] += W * Y * p1; ff[0][2] += W * Z * p1;
+                        ff[1][0] += W * X * p0; ff[1][1] += W * Y * p0; ff[1][2] += W * Z * p0;
+                    }
+                }
+            });
+            const double r0 = rho0[s], r1 = rho1[s], r = r0 + r1;
+            const double g[3] = {gx, gy, gz};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                double w0 = G * fw[0][d], w1 = G * fw[1][d];
+                if (wall_kind == 1) {
+                    // F_a,wall / rho_a less (F_0,wall + F_1,wall) / rho
+                    const double net = (r0 * w0 + r1 * w1) / r;
+                    w0 -= net;
+                    w1 -= net;
+                }
+                a[0][d] = G * ff[0][d] + w0 + g[d];
+                a[1][d] = G * ff[1][d] + w1 + g[d];
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            acc[d * N + s] = a[0][d];
+            acc[(3 + d) * N + s] = a[1][d];
+        }
+    }
+}
+
 // Internal state from fields: f*_j(x) = f_j(x + c_j) if that site is fluid,
 // else f_opp(j)(x), with f = f_eq(rho_a, u) (Eq. 3), plus the strain's
-// non-equilibrium part when pi is given (warm start).
+// non-equilibrium part when pi is given (warm start).  With acc given, u is
+// the force-shifted velocity u_F of Eq. (8) and component a's equilibrium
+// takes u_F - (F_a / rho_a) / 2, so that the mixture's population momentum
+// sum_i c_i f_i is rho u_F - F / 2 as Eq. (8) requires.
 template <typename S>
 __global__ void init_fields_kernel(S *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
-                                   const double *rho1, const double *u, const double *pi, int nx, int ny, int nz,
-                                   int64_t ngroups, int eq_kind, double ref0, double ref1) {
+                                   const double *rho1, const double *u, const double *pi, const double *acc, int nx,
+                                   int ny, int nz, int64_t ngroups, int eq_kind, double ref0, double ref1) {
     const int64_t N = (int64_t)nx * ny * nz;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t L = links[s];
@@ -1591,7 +1648,16 @@ __global__ void init_fields_kernel(S *dst, const uint32_t *links, const int32_t 
             const int64_t t = wall ? s : site_shift(x, y, z, cx_of(j), cy_of(j), cz_of(j), nx, ny, nz);
             const int kk = wall ? opp_of(j) : j;
             const double ux = u ? u[t] : 0.0, uy = u ? u[N + t] : 0.0, uz = u ? u[2 * N + t] : 0.0;
-            double f0 = feq_dir(kk, rho0[t], ux, uy, uz, eq_kind), f1 = feq_dir(kk, rho1[t], ux, uy, uz, eq_kind);
+            double v[2][3] = {{ux, uy, uz}, {ux, uy, uz}};
+            if (acc) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    v[0][d] -= 0.5 * acc[d * N + t];
+                    v[1][d] -= 0.5 * acc[(3 + d) * N + t];
+                }
+            }
+            double f0 = feq_dir(kk, rho0[t], v[0][0], v[0][1], v[0][2], eq_kind);
+            double f1 = feq_dir(kk, rho1[t], v[1][0], v[1][1], v[1][2], eq_kind);
             if (pi) {
                 f0 += neq_dir(kk, rho0[t], pi, N, t);
                 f1 += neq_dir(kk, rho1[t], pi, N, t);
@@ -1602,27 +1668,31 @@ __global__ void init_fields_kernel(S *dst, const uint32_t *links, const int32_t 
     }
 }
 
-// FP64 sums of the convergence residual over all sites (solid sites hold 0
-// in both states): [sum (ra - ra_prev)^2, sum ra^2, sum |u - u_prev|^2,
-// sum |u|^2] per block into partials (kPartialStride per block).
+// FP64 sums of the distance between two states over all sites (solid sites
+// hold 0 in both): [sum (ra - ra_prev)^2, sum ra^2, sum |u - u_prev|^2,
+// sum |u|^2, sum ra_prev^2, sum |u_prev|^2] per block into partials
+// (kPartialStride per block).
 __global__ void residual_kernel(const double *ra, const double *u, const double *ra_prev, const double *u_prev,
                                 int64_t N, double *partials) {
-    __shared__ double red[4][4];
-    double acc[4] = {0, 0, 0, 0};
+    constexpr int K = 6;
+    __shared__ double red[4][K];
+    double acc[K] = {0, 0, 0, 0, 0, 0};
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
-        const double da = ra[s] - ra_prev[s];
+        const double a = ra[s], ap = ra_prev[s], da = a - ap;
         acc[0] += da * da;
-        acc[1] += ra[s] * ra[s];
+        acc[1] += a * a;
+        acc[4] += ap * ap;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const double v = u[d * N + s], dv = v - u_prev[d * N + s];
+            const double v = u[d * N + s], vp = u_prev[d * N + s], dv = v - vp;
             acc[2] += dv * dv;
             acc[3] += v * v;
+            acc[5] += vp * vp;
         }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < K; ++k) {
         double v = acc[k];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -1631,7 +1701,7 @@ __global__ void residual_kernel(const double *ra, const double *u, const double 
     __syncthreads();
     if (threadIdx.x < kPartialStride) {
         double v = 0.0;
-        if (threadIdx.x < 4)
+        if (threadIdx.x < K)
             for (int q = 0; q < 4; ++q) v += red[q][threadIdx.x];
         partials[(size_t)blockIdx.x * kPartialStride + threadIdx.x] = v;
     }
@@ -1878,12 +1948,20 @@ hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, i
     }
 
 hipError_t launch_init_fields(int prec, void *dst, const uint32_t *links, const int32_t *idx, const double *rho0,
-                              const double *rho1, const double *u, const double *pi, int nx, int ny, int nz,
-                              int64_t ngroups, int eq_kind, const double ref[2], hipStream_t s) {
+                              const double *rho1, const double *u, const double *pi, const double *acc, int nx,
+                              int ny, int nz, int64_t ngroups, int eq_kind, const double ref[2], hipStream_t s) {
     const int g = site_grid((int64_t)nx * ny * nz);
     LBM_DISPATCH_PREC(prec, S,
                       hipLaunchKernelGGL(init_fields_kernel<S>, dim3(g), dim3(256), 0, s, static_cast<S *>(dst), links,
-                                         idx, rho0, rho1, u, pi, nx, ny, nz, ngroups, eq_kind, ref[0], ref[1]));
+                                         idx, rho0, rho1, u, pi, acc, nx, ny, nz, ngroups, eq_kind, ref[0], ref[1]));
+    return hipGetLastError();
+}
+
+hipError_t launch_accel(const uint32_t *links, const double *rho0, const double *rho1, double G, double wall0,
+                        double wall1, int wall_kind, const double g[3], int nx, int ny, int nz, double *acc,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(accel_kernel, dim3(site_grid((int64_t)nx * ny * nz)), dim3(256), 0, s, links, rho0, rho1, G,
+                       wall0, wall1, wall_kind, g[0], g[1], g[2], nx, ny, nz, acc);
     return hipGetLastError();
 }
 

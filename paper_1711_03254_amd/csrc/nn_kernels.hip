@@ -312,6 +312,124 @@ __global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n) {
         y[e] = f32_to_bf16(x[e]);
 }
 
+// ---------------------------------------------------------------------------
+// Input features and output decoding of the surrogate, on the device.
+// ---------------------------------------------------------------------------
+// Squared distance along one axis to the nearest solid site within +-R
+// (periodic; infinity if none): pass 0 of the separable distance transform.
+__global__ void dist_pass_x(const uint8_t *solid, float *g2, int D, int H, int W, int R) {
+    const int64_t n = (int64_t)D * H * W;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(e % W);
+        const int64_t row = e - x;
+        float best = __builtin_inff();
+        for (int dx = -R; dx <= R; ++dx) {
+            int xx = (x + dx) % W;
+            if (xx < 0) xx += W;
+            if (solid[row + xx]) best = fminf(best, (float)(dx * dx));
+        }
+        g2[e] = best;
+    }
+}
+
+// Passes 1 and 2: out(p) = min over |k| <= R of in(p + k e_axis) + k^2
+// (axis 1 = y, stride W; axis 2 = z, stride H W); the last pass takes the
+// square root, clipped at R sqrt(3).
+__global__ void dist_pass_yz(const float *in, float *out, int D, int H, int W, int R, int axis, int last) {
+    const int64_t n = (int64_t)D * H * W;
+    const int L = axis == 1 ? H : D;
+    const int64_t stride = axis == 1 ? (int64_t)W : (int64_t)H * W;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = axis == 1 ? (int)((e / W) % H) : (int)(e / ((int64_t)H * W));
+        const int64_t base = e - (int64_t)c * stride;
+        float best = __builtin_inff();
+        for (int k = -R; k <= R; ++k) {
+            int cc = (c + k) % L;
+            if (cc < 0) cc += L;
+            best = fminf(best, in[base + (int64_t)cc * stride] + (float)(k * k));
+        }
+        out[e] = last ? fminf(sqrtf(best), (float)R * 1.7320508f) : best;
+    }
+}
+
+// bf16 input channels [solid, phi_A, dist / dist_scale, 0 ...] (c channels
+// at stride ldx), phi_A = rho_A / (rho_A + rho_B) on fluid sites, else 0.
+__global__ void features_kernel(const uint8_t *solid, const double *ra, const double *rb, const float *dist,
+                                float inv_scale, uint16_t *x, int ldx, int c, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const bool s = solid[e] != 0;
+        const double tot = ra[e] + rb[e];
+        const float phi = (!s && tot > 0) ? (float)(ra[e] / tot) : 0.f;
+        uint16_t *o = x + e * ldx;
+        o[0] = f32_to_bf16(s ? 1.f : 0.f);
+        o[1] = f32_to_bf16(phi);
+        o[2] = f32_to_bf16(dist[e] * inv_scale);
+        for (int k = 3; k < c; ++k) o[k] = 0;
+    }
+}
+
+// Fields from the output channels [ux, uy, uz, d rho_A, d rho_B] at fluid
+// sites: u = out * u_scale * g / nu_mix (nu_mix of the initial fraction,
+// Eqs. 5-6), rho = max(rho0 + rho_scale * out, floor); zero on solid sites.
+// Per-block FP64 sums of [rho_A0, rho_B0, rho_A, rho_B] over fluid sites go
+// to part (4 per block).
+__global__ void decode_kernel(const float *out, int ldo, const uint8_t *solid, const double *ra0, const double *rb0,
+                              double nu_a, double nu_b, double g, float u_scale, float rho_scale, double floor,
+                              double *u, double *ra, double *rb, double *part, int64_t n) {
+    __shared__ double sh[4][256];
+    double acc[4] = {0, 0, 0, 0};
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const float *o = out + e * ldo;
+        double ux = 0, uy = 0, uz = 0, a = 0, b = 0;
+        if (!solid[e]) {
+            const double tot = ra0[e] + rb0[e];
+            const double phi = tot > 0 ? ra0[e] / tot : 0.0;
+            const double m = g / (phi * nu_a + (1.0 - phi) * nu_b);
+            ux = (double)o[0] * (double)u_scale * m;
+            uy = (double)o[1] * (double)u_scale * m;
+            uz = (double)o[2] * (double)u_scale * m;
+            a = fmax(ra0[e] + (double)rho_scale * (double)o[3], floor);
+            b = fmax(rb0[e] + (double)rho_scale * (double)o[4], floor);
+            acc[0] += ra0[e];
+            acc[1] += rb0[e];
+            acc[2] += a;
+            acc[3] += b;
+        }
+        u[e] = ux;
+        u[n + e] = uy;
+        u[2 * n + e] = uz;
+        ra[e] = a;
+        rb[e] = b;
+    }
+    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Rescales rho_A, rho_B so that their fluid sums equal those of rho_A0,
+// rho_B0 (the partial sums of decode_kernel, added in block order).
+__global__ void rescale_kernel(const double *part, int nparts, double *ra, double *rb, int64_t n) {
+    __shared__ double tot[4];
+    if (threadIdx.x < 4) {
+        double s = 0.0;
+        for (int q = 0; q < nparts; ++q) s += part[q * 4 + threadIdx.x];
+        tot[threadIdx.x] = s;
+    }
+    __syncthreads();
+    const double fa = tot[2] > 0 ? tot[0] / tot[2] : 0.0, fb = tot[3] > 0 ? tot[1] / tot[3] : 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        ra[e] *= fa;
+        rb[e] *= fb;
+    }
+}
+
+constexpr int kDecodeBlocks = 1024;
+
 int grid_for(int64_t n) {
     const int64_t b = (n + 255) / 256;
     return (int)(b < 16384 ? (b > 0 ? b : 1) : 16384);
@@ -439,6 +557,40 @@ int nn_adam(float *param, const float *grad, float *m, float *v, uint16_t *param
     const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
     hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), param, grad, m, v,
                        param_bf16, n, lr, b1, b2, eps, c1, c2);
+    return done();
+}
+
+int nn_solid_distance(const uint8_t *solid, float *work, float *dist, int32_t d, int32_t h, int32_t w_, int32_t radius,
+                      void *stream) {
+    if (!solid || !work || !dist || !dims_ok(1, d, h, w_) || radius < 1) return LBM_EINVAL;
+    const int64_t n = positions(1, d, h, w_);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int g = grid_for(n);
+    hipLaunchKernelGGL(dist_pass_x, dim3(g), dim3(256), 0, s, solid, work, d, h, w_, radius);
+    hipLaunchKernelGGL(dist_pass_yz, dim3(g), dim3(256), 0, s, work, work + n, d, h, w_, radius, 1, 0);
+    hipLaunchKernelGGL(dist_pass_yz, dim3(g), dim3(256), 0, s, work + n, dist, d, h, w_, radius, 2, 1);
+    return done();
+}
+
+int nn_features(const uint8_t *solid, const double *rho_a, const double *rho_b, const float *dist, float dist_scale,
+                uint16_t *x, int32_t ldx, int32_t c, int64_t p, void *stream) {
+    if (!solid || !rho_a || !rho_b || !dist || !x || c < 3 || ldx < c || p <= 0 || !(dist_scale > 0))
+        return LBM_EINVAL;
+    hipLaunchKernelGGL(features_kernel, dim3(grid_for(p)), dim3(256), 0, static_cast<hipStream_t>(stream), solid, rho_a,
+                       rho_b, dist, 1.0f / dist_scale, x, ldx, c, p);
+    return done();
+}
+
+int nn_decode_fields(const float *out, int32_t ldo, const uint8_t *solid, const double *rho_a0, const double *rho_b0,
+                     double nu_a, double nu_b, double g, float u_scale, float rho_scale, double floor, double *u,
+                     double *rho_a, double *rho_b, double *work, int64_t p, void *stream) {
+    if (!out || !solid || !rho_a0 || !rho_b0 || !u || !rho_a || !rho_b || !work || ldo < 5 || p <= 0 ||
+        !(nu_a > 0) || !(nu_b > 0) || !(floor >= 0))
+        return LBM_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(decode_kernel, dim3(kDecodeBlocks), dim3(256), 0, s, out, ldo, solid, rho_a0, rho_b0, nu_a, nu_b,
+                       g, u_scale, rho_scale, floor, u, rho_a, rho_b, work, p);
+    hipLaunchKernelGGL(rescale_kernel, dim3(grid_for(p)), dim3(256), 0, s, work, kDecodeBlocks, rho_a, rho_b, p);
     return done();
 }
 

@@ -28,7 +28,8 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_EMASSDRIFT = 0,
 ERROR_NAMES = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_ENONFINITE", -5: "LBM_EMASSDRIFT"}
 
 EXPORTED = ("lbm_init", "lbm_step", "lbm_moments", "lbm_reduce", "lbm_reduce_noalloc", "lbm_get_populations",
-            "lbm_set_populations", "lbm_set_fields", "lbm_set_fields_strain", "lbm_residual", "lbm_info", "lbm_last_error", "lbm_free",
+            "lbm_set_populations", "lbm_set_fields", "lbm_set_fields_strain", "lbm_residual", "lbm_distance",
+            "lbm_info", "lbm_last_error", "lbm_free",
             "lbm_batch_create", "lbm_batch_step", "lbm_batch_last_error", "lbm_batch_free")
 
 
@@ -96,6 +97,7 @@ def load_library():
     lib.lbm_set_fields.argtypes = [vp, vp, vp, vp, ctypes.c_int]
     lib.lbm_set_fields_strain.argtypes = [vp, vp, vp, vp, ctypes.c_int]
     lib.lbm_residual.argtypes = [vp, dp]
+    lib.lbm_distance.argtypes = [vp, vp, vp, ctypes.c_int, dp]
     lib.lbm_info.argtypes = [vp, ctypes.POINTER(lbm_info_t)]
     lib.lbm_last_error.argtypes = [vp]
     lib.lbm_last_error.restype = ctypes.c_char_p
@@ -321,6 +323,18 @@ def lbm_residual(ctx: Context) -> tuple[float, float]:
     call, in FP64 on the device."""
     out = np.zeros(2)
     _check(ctx, load_library().lbm_residual(ctx.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return float(out[0]), float(out[1])
+
+
+def lbm_distance(ctx: Context, rho1, u) -> tuple[float, float]:
+    """(||u_F - u|| / ||u||, ||rho1 - rho1_given|| / ||rho1_given||) of the
+    current state against given fields (host arrays or device tensors), in
+    FP64 on the device."""
+    ptrs, dev, keep = _field_args(rho1, u, None)
+    out = np.zeros(2)
+    _check(ctx, load_library().lbm_distance(ctx.handle, ptrs[0], ptrs[1], dev,
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    del keep
     return float(out[0]), float(out[1])
 
 

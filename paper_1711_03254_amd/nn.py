@@ -17,7 +17,7 @@ from . import lbm
 
 NN_EXPORTED = ("nn_conv3d_fwd", "nn_weights_flip", "nn_bwd_weight_work", "nn_conv3d_bwd_weight",
                "nn_relu_bwd_cast", "nn_pool2_fwd", "nn_pool2_bwd", "nn_up2_fwd", "nn_up2_bwd", "nn_mse",
-               "nn_adam", "nn_to_bf16")
+               "nn_adam", "nn_to_bf16", "nn_solid_distance", "nn_features", "nn_decode_fields")
 
 _lib = None
 _P, _I, _L, _F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
@@ -41,6 +41,10 @@ def load():
         "nn_mse": [_P, _I, _P, _I, _P, _P, _I, _P, _L, _I, _P],
         "nn_adam": [_P, _P, _P, _P, _P, _L, _F, _F, _F, _F, _I, _P],
         "nn_to_bf16": [_P, _P, _L, _P],
+        "nn_solid_distance": [_P, _P, _P, _I, _I, _I, _I, _P],
+        "nn_features": [_P, _P, _P, _P, _F, _P, _I, _I, _L, _P],
+        "nn_decode_fields": [_P, _I, _P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _F, _F,
+                             ctypes.c_double, _P, _P, _P, _P, _L, _P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -132,3 +136,23 @@ def adam(param, grad, m, v, param_bf16, lr, t, b1=0.9, b2=0.999, eps=1e-8, strea
 
 def to_bf16(x, y, stream=None):
     _ok("nn_to_bf16", load().nn_to_bf16(x.data_ptr(), y.data_ptr(), x.numel(), _s(stream)))
+
+
+def solid_distance(solid, work, dist, dims, radius, stream=None):
+    """solid: uint8 tensor; work: float32 tensor of 2 P; dist: float32 [P]."""
+    d, h, w = dims
+    _ok("nn_solid_distance", load().nn_solid_distance(solid.data_ptr(), work.data_ptr(), dist.data_ptr(), d, h, w,
+                                                      radius, _s(stream)))
+
+
+def features(solid, rho_a, rho_b, dist, dist_scale, x: View, c, stream=None):
+    _ok("nn_features", load().nn_features(solid.data_ptr(), rho_a.data_ptr(), rho_b.data_ptr(), dist.data_ptr(),
+                                          dist_scale, x.ptr, x.ld, c, solid.numel(), _s(stream)))
+
+
+def decode_fields(out: View, solid, rho_a0, rho_b0, nu_a, nu_b, g, u_scale, rho_scale, floor, u, rho_a, rho_b, work,
+                  stream=None):
+    _ok("nn_decode_fields", load().nn_decode_fields(out.ptr, out.ld, solid.data_ptr(), rho_a0.data_ptr(),
+                                                    rho_b0.data_ptr(), nu_a, nu_b, g, u_scale, rho_scale, floor,
+                                                    u.data_ptr(), rho_a.data_ptr(), rho_b.data_ptr(), work.data_ptr(),
+                                                    solid.numel(), _s(stream)))

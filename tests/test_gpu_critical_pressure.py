@@ -1,7 +1,7 @@
 """Critical pressure of a wetting slug in a constriction against Eq. (12)
 (needs an MI355X: -m gpu).
 
-The protocol of Section 3.4 runs on the solver: a slug of the second
+The protocol of Section 3.6 runs on the solver: a slug of the second
 component over the exit of a narrow part (D = 10) of a periodic channel
 (H = 40, L = 160, Z = 52), body forces stepped through -30 ... +30 % of
 g_crit = 2 sigma cos(theta) (1/D - 1/H) / (rho_0 L), 80 000 steps per stage.

@@ -138,12 +138,19 @@ def test_network_gradients_match_fp64(mods, emulate_storage):
 
     With emulate_storage the reference rounds to BF16 wherever the GPU path
     stores BF16 (activations, the gradient at each convolution output): the
-    two then differ only by FP32 accumulation order and the BF16 roundings
-    that it flips (each a 2^-8 relative change of one element, carried on
-    through the later layers); the bar is the 1e-2 of a BF16 gradient check
-    (measured: at most 3e-3).  Without it the comparison states the cost of
-    BF16 storage against exact arithmetic: about two roundings of relative
-    size 2^-9 per layer over nine layers, bound 5e-2 (measured: 3e-2)."""
+    two then differ by FP32 accumulation order and the BF16 roundings it
+    flips, each flip a 2^-8 relative change of one element (or a ReLU mask
+    bit), carried on through the later layers.  Over twelve layers at 16^3
+    that noise is large: two FP64 reference runs whose stored values differ
+    only by a 1e-7 relative jitter before rounding give layer gradients
+    1.2-3 % and the input gradient 4.2 % apart; measured GPU against the
+    reference: layers at most 2.2 %, input gradient 3.5 %.  Without
+    emulation the comparison states the cost of BF16 storage against exact
+    arithmetic (reference against itself: layers 2.6 %, input gradient
+    5.1 %).  Bars: 5e-2 for the output, the loss and every layer, 8e-2 for
+    the input gradient (not used in training); a wiring mistake (a skip
+    connection, a level, a transposed weight) gives errors of order one.
+    """
     torch, nn, sg = mods
     base = 16
     net = sg.Surrogate(base=base, seed=3)
@@ -152,8 +159,10 @@ def test_network_gradients_match_fp64(mods, emulate_storage):
     for name, ci, co, _ in net.spec:   # non-zero biases so that their gradients are checked too
         w0, b0 = net.offsets[name]
         flat[b0:b0 + co] = rng.normal(scale=0.05, size=co)
+        if name == "out":   # He scale for every layer (training starts the output layer 10x smaller)
+            flat[w0:b0] *= 10.0
     net.set_params(flat.astype(np.float32))
-    dims = (1, 8, 8, 8)
+    dims = (1, 16, 16, 16)
     P = int(np.prod(dims))
     x = np.zeros(dims + (sg.CIN,))
     x[..., 0] = rng.random(dims) < 0.3
@@ -190,29 +199,94 @@ def test_network_gradients_match_fp64(mods, emulate_storage):
         errs[name] = (rel(grads[w0:b0].reshape(27, co, ci), ref_g[name][0]), rel(grads[b0:b0 + co], ref_g[name][1]))
     e_dx = rel(net.G["x"].cpu().numpy().reshape(ref_dx.shape)[..., :2], ref_dx[..., :2])
     record("nn_network_gradients", emulate_storage=emulate_storage, out=e_out, loss=e_loss, dx=e_dx, layers=errs)
-    tol = 1e-2 if emulate_storage else 5e-2
-    assert e_out <= tol and e_loss <= tol and e_dx <= tol
+    tol = 5e-2
+    assert e_out <= tol and e_loss <= tol and e_dx <= 8e-2
     for name, (ew, eb) in errs.items():
         assert ew <= tol and eb <= tol, (name, ew, eb)
 
 
 def test_training_lowers_the_loss(mods):
     """Adam on the GPU kernels fits a fixed target from features: the loss
-    falls to under a third of its start in 300 steps (measured: 0.22)."""
+    falls to under a third of its start in 600 steps."""
     torch, nn, sg = mods
     net = sg.Surrogate(base=16, seed=4)
     dims = (1, 16, 16, 16)
     rng = np.random.default_rng(11)
     solid = (rng.random(dims[1:]) < 0.3).astype(np.float64)
     phi = rng.random(dims[1:])
-    x = sg.features(solid, phi)
+    x = sg.features(solid, phi, 1.0 - phi)
     # a smooth target built from the features
     u = np.stack([phi * (1 - solid), 0.5 * phi, (1 - solid) * 0.2])
     t = sg.targets(u, 1 - solid, phi, 1.0, np.ones(solid.size), 0.0, 0.0)
     cw = sg.loss_weights()
     first = float(net.train_step(x, t, cw, dims, 3e-3))
-    for _ in range(300):
+    for _ in range(600):
         last = net.train_step(x, t, cw, dims, 3e-3)
     last = float(last)
     record("nn_training", first=first, last=last)
     assert np.isfinite(last) and last < first / 3
+
+
+def test_solid_distance_and_features_on_the_gpu(mods):
+    """nn_solid_distance against the exact periodic Euclidean distance
+    transform (scipy on a 3 x 3 x 3 tiling of the mask, centre block) where
+    that distance is within the kernel's radius, and nn_features against
+    the channels it is defined by (bf16 of the mask, the fraction of A and
+    the distance / 8)."""
+    torch, nn, sg = mods
+    from scipy import ndimage
+    from paper_1711_03254_amd import inputs
+    n = 48
+    solid, ra0, rb0, _ = inputs.mixture_case(n, 5, radius_range=(3.0, 8.0))
+    big = np.tile(solid != 0, (3, 3, 3))
+    want = ndimage.distance_transform_edt(~big)[n:2 * n, n:2 * n, n:2 * n]
+    s = torch.from_numpy(solid).cuda().reshape(-1)
+    work = torch.empty(2 * s.numel(), dtype=torch.float32, device="cuda")
+    dist = torch.empty(s.numel(), dtype=torch.float32, device="cuda")
+    nn.solid_distance(s, work, dist, solid.shape, sg.DIST_RADIUS)
+    got = dist.cpu().numpy().astype(np.float64).reshape(solid.shape)
+    inside = want <= sg.DIST_RADIUS
+    assert inside.mean() > 0.99
+    np.testing.assert_allclose(got[inside], want[inside], rtol=1e-6, atol=0)
+    x = sg.features(solid, ra0, rb0).cpu().numpy().view(np.uint16).reshape(-1, sg.CIN)
+    vals = (x.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    tot = ra0 + rb0
+    phi = np.where((solid == 0) & (tot > 0), ra0 / np.where(tot > 0, tot, 1.0), 0.0)
+    for k, ref in ((0, (solid != 0).astype(np.float64)), (1, phi), (2, want / sg.DIST_SCALE)):
+        ref = bf16_round(ref.reshape(-1))
+        m = inside.reshape(-1)
+        np.testing.assert_allclose(vals[m, k], ref[m], rtol=2.0 ** -8, atol=0)
+    assert not vals[:, 3:].any()
+
+
+def test_decode_fields_matches_its_definition(mods):
+    """nn_decode_fields against the warm state written out in NumPy: velocity
+    from the output in units of u_scale g / nu_mix, densities floored and
+    rescaled to the initial masses, zero on solid sites."""
+    torch, nn, sg = mods
+    rng = np.random.default_rng(21)
+    shape = (8, 12, 16)
+    P = int(np.prod(shape))
+    solid = (rng.random(shape) < 0.35).astype(np.uint8)
+    ra0 = np.where(solid == 1, 0.0, rng.uniform(0.1, 0.9, shape))
+    rb0 = np.where(solid == 1, 0.0, 1.0 - ra0)
+    out = rng.normal(size=(P, sg.COUT)).astype(np.float32)
+    out[:, 3:5] *= 3.0
+    nu, g, us, rs, floor = (0.02, 0.15), 1e-5, 2.5, 0.05, 1e-3
+
+    class Net:
+        u_scale, rho_scale = us, rs
+    u, ra, rb = sg.decode_device(Net, torch.from_numpy(out.reshape(-1)).cuda(), solid, ra0, rb0, nu, g, floor)
+    f = (solid == 0).reshape(-1)
+    tot = (ra0 + rb0).reshape(-1)
+    phi = np.where(tot > 0, ra0.reshape(-1) / np.where(tot > 0, tot, 1.0), 0.0)
+    m = g / (phi * nu[0] + (1 - phi) * nu[1])
+    o = out.astype(np.float64)
+    want_u = np.where(f[None], (o[:, 0:3] * np.float64(np.float32(us))).T * m, 0.0)
+    wa = np.where(f, np.maximum(ra0.reshape(-1) + np.float64(np.float32(rs)) * o[:, 3], floor), 0.0)
+    wb = np.where(f, np.maximum(rb0.reshape(-1) + np.float64(np.float32(rs)) * o[:, 4], floor), 0.0)
+    wa *= ra0.reshape(-1)[f].sum() / wa[f].sum()
+    wb *= rb0.reshape(-1)[f].sum() / wb[f].sum()
+    np.testing.assert_allclose(u.cpu().numpy().reshape(3, -1), want_u, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(ra.cpu().numpy(), wa, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(rb.cpu().numpy(), wb, rtol=1e-12, atol=0)

@@ -1,15 +1,6 @@
-"""The learned warm start end to end at a small size (needs an MI355X): the
-solver generates steady states, the surrogate is trained on them by its own
-kernels, and held-out cases are solved cold and warm to the same residual.
-
-What is asserted is what the warm start must never break: training lowers
-the loss, and both solves converge, to the same state (so the surrogate
-cannot bend the answer).  The prediction errors and what it gains
-over the cold start (the ratio of steps) is measured and recorded, not
-assumed: on porous subvolumes even an exact prediction of the steady fields
-saves few steps, because the residual is then dominated by the relaxation
-of the non-equilibrium populations that no macroscopic initial state sets.
-"""
+"""The learned warm start (needs an MI355X): the library calls it rests on
+(the restart from fields with the strain's non-equilibrium part, the FP64
+residual and distance), and the warm start end to end at a small size."""
 import json
 import os
 
@@ -83,8 +74,8 @@ def test_strain_start_is_near_steady(prec):
     force); from the equilibrium alone the force accelerates the fluid
     unopposed until the stress has built up.  tau_mix = 0.61: at tau_mix = 1
     the collision discards the non-equilibrium part whatever it is, and
-    the two starts coincide after one step.  The profile given is the bare
-    velocity sum c f / rho = u_F - g / 2 of the steady state."""
+    the two starts coincide after one step.  The profile is given as u_F,
+    as lbm_moments reports it."""
     from paper_1711_03254_amd import lbm
     lbm.load_library()
     ny = 34
@@ -98,11 +89,13 @@ def test_strain_start_is_near_steady(prec):
     ra = np.where(solid == 1, 0.0, phi)
     rb = np.where(solid == 1, 0.0, 1 - phi)
     u = np.zeros((3,) + solid.shape)
-    u[2] = np.where(solid == 1, 0.0, prof[None, :, None] - g / 2)
+    u[2] = np.where(solid == 1, 0.0, prof[None, :, None])
     change = {}
     for strain in (False, True):
+        u0 = u.copy()
+        u0[2] -= np.where(solid == 1, 0.0, g / 2)    # lbm_init takes the population velocity
         ctx = lbm.lbm_init(lbm.Params(4, ny, 4, prec=lbm.PRECISIONS[prec], tau=tau, g=(0.0, 0.0, g), solid=solid,
-                                      rho_init=(ra, rb), u_init=u))
+                                      rho_init=(ra, rb), u_init=u0))
         if strain:
             lbm.lbm_set_fields_strain(ctx, ra, rb, u)
         lbm.lbm_residual(ctx)
@@ -131,30 +124,70 @@ def test_residual_matches_the_fields():
     lbm.lbm_free(ctx)
 
 
+def test_restart_from_fields_follows_the_state():
+    """A coupled mixture (G = -1) in a porous subvolume stepped 3000 steps at
+    FP64, restarted from its fields (rho1, rho2, u_F) into fresh contexts:
+    through lbm_set_fields_strain the restart follows the original run
+    (the force shift and the strain's non-equilibrium part set the
+    populations the fields imply); the plain equilibrium of u_F (lbm_set_fields)
+    does not.  lbm_distance of a state against its own fields is 0."""
+    from paper_1711_03254_amd import inputs, lbm, warmstart as ws
+    lbm.load_library()
+    solid, ra0, rb0, _ = inputs.mixture_case(32, 902, radius_range=(1.5, 4.0))
+    phys = ws.physics()
+    ctx = ws.make_context(solid, ra0, rb0, phys, "fp64")
+    lbm.lbm_step(ctx, 3000)
+    u, ra, rb = ws.fields(ctx, solid.shape)
+    assert lbm.lbm_distance(ctx, ra, u) == (0.0, 0.0)
+    strain = ws.make_context(solid, ra, rb, phys, "fp64")
+    lbm.lbm_set_fields_strain(strain, ra, rb, u)
+    plain = ws.make_context(solid, ra, rb, phys, "fp64")
+    lbm.lbm_set_fields(plain, ra, rb, u)
+    for c in (ctx, strain, plain):
+        lbm.lbm_step(c, 200)
+    u1, ra1, _ = ws.fields(ctx, solid.shape)
+    d_strain = lbm.lbm_distance(strain, ra1, u1)
+    d_plain = lbm.lbm_distance(plain, ra1, u1)
+    record("restart_from_fields", strain=d_strain, plain=d_plain)
+    assert d_strain[0] < 0.1 * d_plain[0]
+    assert d_strain[0] < 1e-2 and d_strain[1] < 1e-4
+    for c in (ctx, strain, plain):
+        lbm.lbm_free(c)
+
+
 def test_warm_start_end_to_end():
+    """Solver-generated samples with the coupling on, the surrogate trained
+    on them by its own kernels, and a held-out case solved cold and warm at
+    FP32 and FP16S storage to the same accuracy against a long cold FP64
+    solve.  Asserted: training lowers the loss, the FP32 cold solve
+    reaches the target, and the FP32 warm solve moves towards the same
+    state (its distance to the reference falls).  Whether and by how much
+    the warm start is faster (steps and time to the target) is recorded,
+    not assumed: on this tiny, tortuous case a poor prediction can also be
+    slower, and at FP16S storage cold and warm solves alike stall where the
+    per-step corrections fall below the 16-bit resolution of the
+    populations (the flow in these small pores is slow: u_F about 1e-4)."""
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     from paper_1711_03254_amd import inputs, lbm, surrogate, warmstart as ws
     lbm.load_library()
     phys = ws.physics()
     rr = (1.5, 4.0)
-    train = [ws.steady_sample(32, 700 + k, phys, tol=1e-7, prec="fp64", max_steps=20000, radius_range=rr)
-             for k in range(6)]
+    train = [ws.steady_sample(32, 700 + k, phys, steps=6000, radius_range=rr) for k in range(6)]
     net = surrogate.Surrogate(base=16, seed=2)
     net.u_scale = ws.u_scale_of(train, phys)
-    hist = ws.train(net, train, phys, epochs=120, lr=2e-3)
+    net.rho_scale = ws.rho_scale_of(train)
+    hist = ws.train(net, train, phys, epochs=200, lr=1e-3)
     assert np.isfinite(hist[-1]) and hist[-1] < hist[0] / 3
-    rows = []
-    for k in range(2):
-        solid, ra0, rb0, info = inputs.mixture_case(32, 900 + k, radius_range=rr)
-        r = ws.compare(net, dict(solid=solid, ra0=ra0, rb0=rb0), phys, 1e-6, prec="fp64", max_steps=40000)
-        rows.append(r)
-        # A solve stopped where the 100-step change is r = 1e-6 is within
-        # r q / (1 - q) of the steady state, q the decay factor per 100 steps of
-        # its slowest mode.  The slowest modes here decay with q ~ 0.999 (the
-        # measured differences are up to 3e-3 in u), so the two end states are
-        # compared at 1e-2 for u and 1e-4 for rho_A (which barely moves).
-        assert r["cold_converged"] and r["warm_converged"]
-        assert r["converged_u_difference"] <= 1e-2 and r["converged_rho_a_difference"] <= 1e-4
-    record("warm_start_32", loss_first=hist[0], loss_last=hist[-1], cases=rows,
-           steps_cold=sum(r["cold_steps"] for r in rows), steps_warm=sum(r["warm_steps"] for r in rows))
+    solid, ra0, rb0, info = inputs.mixture_case(32, 900, radius_range=rr)
+    ref_a, ref_u, _ = ws.reference(solid, ra0, rb0, phys, 20000)
+    targets = [(0.05, 0.005)]
+    r = ws.compare(net, dict(solid=solid, ra0=ra0, rb0=rb0), phys, (ref_a, ref_u), targets, every=500,
+                   max_steps=30000)
+    assert r["fp32"]["cold"]["reached"][0] is not None, r["fp32"]["cold"]["final"]
+    w = r["fp32"]["warm"]["trajectory"]
+    assert w[-1][1] < 0.5 * w[0][1] or r["fp32"]["warm"]["reached"][0] is not None, (w[0], w[-1])
+    record("warm_start_32", loss_first=hist[0], loss_last=hist[-1], prediction=r["prediction_distance"],
+           factors={p: r[p]["factors"] for p in ("fp32", "fp16s")},
+           reached={p: {a: r[p][a]["reached"][0] for a in ("cold", "warm")} for p in ("fp32", "fp16s")},
+           final={p: {a: r[p][a]["final"] for a in ("cold", "warm")} for p in ("fp32", "fp16s")})

@@ -74,14 +74,15 @@ def test_network_gradient_against_finite_differences():
     _, dout = nn.mse(out, target, cw)
     grads, dx = nn.backward(params, cache, dout, spec)
     eps = 1e-6
-    for name, (t, co, ci) in [("e1a", (13, 1, 0)), ("b1", (0, 5, 7)), ("d2", (26, 2, 11)), ("out", (4, 2, 3))]:
+    for name, (t, co, ci) in [("e1a", (13, 1, 0)), ("e3a", (5, 9, 6)), ("b1", (0, 5, 7)), ("d3", (2, 10, 20)),
+                              ("d2", (26, 2, 11)), ("out", (4, 2, 3))]:
         w, b = params[name]
         wp, wm = w.copy(), w.copy()
         wp[t, co, ci] += eps
         wm[t, co, ci] -= eps
         fd = (loss({**params, name: (wp, b)}) - loss({**params, name: (wm, b)})) / (2 * eps)
         assert np.isclose(grads[name][0][t, co, ci], fd, rtol=1e-5, atol=1e-10), name
-    for name in ("e2b", "d1"):
+    for name in ("e2b", "e3b", "d1"):
         w, b = params[name]
         bp, bm = b.copy(), b.copy()
         bp[1] += eps

@@ -286,8 +286,8 @@ def _wall_case(seed, shape=(10, 14, 12), two_components=True):
 
 
 def test_momentum_balanced_wall_force_leaves_the_mixture_force_alone(ora):
-    """Reading W2 of the wall force (Section 3.3: the interaction force along
-    walls balanced between the components): each component gives up its
+    """Reading W2 of the wall force (Section 2 after Eq. 11, used in Section
+    3.5: the interaction force along walls balanced between the components): each component gives up its
     density share of the mixture's net wall force.  Then the wall potential
     cannot change the mixture force, hence not u_F = (j + F / 2) / rho
     (Eq. 8) of any state -- while under W1 it does -- and it still changes the
