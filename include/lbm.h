@@ -91,7 +91,9 @@ typedef struct {
     int32_t tile_x, tile_y;      /* x-y tile of the step kernel (0 = library default; 64x4, 32x8,
                                     16x16, 8x32, 64x8, 32x16 or 64x16; FP64 takes the first four
                                     only, others give LBM_EINVAL) */
-    int32_t zchunk;              /* z planes per block (0 = library default) */
+    int32_t zchunk;              /* z planes per block; 0 (default): the library cuts each tile
+                                    column into work items of balanced cost (dense columns into
+                                    more, shorter items), one round of resident blocks */
     int32_t wall_kind;           /* 0: the wall force of Eq. (11) as it stands (W1, default);
                                     1: each component gives up its density share of the mixture's
                                     net wall force, so that the walls separate the components
@@ -202,7 +204,7 @@ int lbm_distance(lbm_ctx *c, const double *r1, const double *u, int on_device, d
 
 /* Facts about a context, for reports: number of fluid sites, steps done,
  * bytes of population storage per site update (read + write), and the
- * step kernel's launch configuration. */
+ * step kernel's launch configuration (zchunk 0: balanced work items). */
 typedef struct {
     int64_t n_sites, n_fluid, steps_done;
     int32_t bytes_per_lu;        /* 2 * 2 * 19 * sizeof(storage) */

@@ -24,6 +24,8 @@ struct lbm_ctx {
     uint32_t *links = nullptr;   // per-site link mask (set-up and exchange kernels)
     int32_t *idx = nullptr;      // compact population index per site, -1 where solid
     int32_t *wstart = nullptr;   // work lists of the step: bounds per tile column and plane
+    int32_t *btab = nullptr;     // balanced work items of the step (4 ints each), or null
+    int nblk = 0;                // their number
     uint16_t *wpos = nullptr;    // work list entries (tile positions of fluid sites)
     double *partials = nullptr;
     double *red_dev = nullptr;
@@ -138,6 +140,91 @@ double default_mass_tol(int prec) {
     }
 }
 
+int device_cus() {
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus;
+}
+
+// Fixed cost of a plane in units of pull jobs, per thread of the block
+// (measured on the 256^3 packed spheres, FP32 and FP16S at 64 x 16:
+// 0, 0.25, 0.5, 1, 2, 4 -> 1 is fastest, 3-4 % below uniform chunks).
+constexpr double kPlaneFixed = 1.0;
+
+// Work items of balanced cost for one launch of the step (4 ints each: tile
+// x, tile y, first plane, end plane).  A block's time grows with the pull
+// jobs of its planes (fluid sites plus the ring of the tile) and a fixed
+// part per plane (barrier, index tile, moments in LDS), plus a start-up of
+// about three planes (pulled one at a time before the pipeline runs).
+// Each tile column is cut greedily into z-ranges of cost at most T (at
+// least four planes each), T the smallest for which the items fit in one
+// round of resident blocks; so dense columns get more, shorter items than
+// sparse ones and the blocks finish together.  Items are ordered by their
+// ordinal within the column, then tile row and column, so that the range
+// of items one XCD receives (xcd_remap) are neighbours.
+std::vector<int32_t> balance_items(const std::vector<int32_t> &wstart, int ntx, int nty, int nz, int tx, int ty,
+                                   int64_t resident) {
+    const int ncol = ntx * nty;
+    const double ring = 2.0 * (tx + 2) + 2.0 * ty, fixed = kPlaneFixed * tx * ty;
+    std::vector<double> cost((size_t)ncol * nz);
+    double total = 0.0;
+    for (int col = 0; col < ncol; ++col)
+        for (int z = 0; z < nz; ++z) {
+            const size_t w = (size_t)col * (nz + 1) + z;
+            const double v = (double)(wstart[w + 1] - wstart[w]) + ring + fixed;
+            cost[(size_t)col * nz + z] = v;
+            total += v;
+        }
+    const double startup = 3.0 * total / ((double)ncol * nz);
+    const int minp = std::min(4, nz);
+    struct Item { int k, col, z0, z1; };
+    auto cut = [&](double T, std::vector<Item> *out) {
+        int64_t items = 0;
+        for (int col = 0; col < ncol; ++col) {
+            const double *cc = cost.data() + (size_t)col * nz;
+            for (int z = 0, k = 0; z < nz; ++k) {
+                double c = startup;
+                int z1 = z;
+                while (z1 < nz && (z1 - z < minp || c + cc[z1] <= T)) c += cc[z1++];
+                if (nz - z1 < minp) z1 = nz;   // no short tail item
+                if (out) out->push_back(Item{k, col, z, z1});
+                ++items;
+                z = z1;
+            }
+        }
+        return items;
+    };
+    double hi = startup;
+    for (int col = 0; col < ncol; ++col) {
+        double s = startup;
+        for (int z = 0; z < nz; ++z) s += cost[(size_t)col * nz + z];
+        hi = std::max(hi, s);
+    }
+    double lo = 0.0;
+    if (cut(hi, nullptr) <= resident)
+        for (int it = 0; it < 60; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (cut(mid, nullptr) <= resident) hi = mid;
+            else lo = mid;
+        }
+    std::vector<Item> items;
+    cut(hi, &items);
+    std::stable_sort(items.begin(), items.end(), [&](const Item &a, const Item &b) {
+        return a.k != b.k ? a.k < b.k : a.col < b.col;
+    });
+    std::vector<int32_t> tab;
+    tab.reserve(items.size() * 4);
+    for (const Item &it : items) {
+        tab.push_back(it.col % ntx);
+        tab.push_back(it.col / ntx);
+        tab.push_back(it.z0);
+        tab.push_back(it.z1);
+    }
+    return tab;
+}
+
 // Launch shape of the step.  fluid: the fraction of fluid sites.
 void choose_launch(lbm_ctx *c, double fluid) {
     const lbm_params &p = c->p;
@@ -164,11 +251,7 @@ void choose_launch(lbm_ctx *c, double fluid) {
         // One round of resident blocks: as many z-chunks as fit beside the
         // tile columns at the kernel's occupancy, each as deep as that
         // allows (fewer chunks re-pull fewer boundary planes).
-        int cus = 0, dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-        const int64_t resident = (int64_t)std::max(lbm::step_blocks_per_cu(p.prec, tx, ty), 1) * cus;
+        const int64_t resident = (int64_t)std::max(lbm::step_blocks_per_cu(p.prec, tx, ty), 1) * device_cus();
         const int64_t xy = (int64_t)c->ntx * c->nty;
         const int64_t chunks = std::max<int64_t>(resident / xy, 1);
         zc = (int)((p.nz + chunks - 1) / chunks);
@@ -191,6 +274,8 @@ lbm::StepLaunch make_launch(const lbm_ctx *c, const void *src, void *dst) {
     L.ngroups = c->ngroups;
     L.tile_x = c->tile_x; L.tile_y = c->tile_y; L.zchunk = c->zchunk;
     L.ntx = c->ntx; L.nty = c->nty; L.nzc = c->nzc;
+    L.btab = c->btab;
+    L.nblk = c->nblk;
     L.tau0 = p.tau[0]; L.tau1 = p.tau[1]; L.G = p.G;
     L.gx = p.g[0]; L.gy = p.g[1]; L.gz = p.g[2];
     L.wall0 = p.rho_s < 0 ? -p.rho_s : 0.0;   // rho^s_1 = -rho^s Theta(-rho^s)
@@ -203,7 +288,7 @@ lbm::StepLaunch make_launch(const lbm_ctx *c, const void *src, void *dst) {
     return L;
 }
 
-int nblocks(const lbm_ctx *c) { return c->ntx * c->nty * c->nzc; }
+int nblocks(const lbm_ctx *c) { return c->btab ? c->nblk : c->ntx * c->nty * c->nzc; }
 
 // FP64 sums of the current state into c->red_host (synchronizes).
 int measure(lbm_ctx *c, double *rho0, double *rho1, double *u) {
@@ -411,7 +496,7 @@ void release(lbm_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (void *q : {c->f[0], c->f[1], (void *)c->links, (void *)c->idx, (void *)c->wstart, (void *)c->wpos,
+    for (void *q : {c->f[0], c->f[1], (void *)c->links, (void *)c->idx, (void *)c->wstart, (void *)c->btab, (void *)c->wpos,
                     (void *)c->partials, (void *)c->red_dev, (void *)c->stage, (void *)c->snap})
         if (q) (void)hipFree(q);
     if (c->red_host) (void)hipHostFree(c->red_host);
@@ -530,7 +615,6 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
     }
     if (hipMalloc(&c->links, sizeof(uint32_t) * c->N) != hipSuccess ||
         hipMalloc(&c->idx, sizeof(int32_t) * c->N) != hipSuccess ||
-        hipMalloc(&c->partials, sizeof(double) * lbm::kPartialStride * nblocks(c)) != hipSuccess ||
         hipMalloc(&c->red_dev, sizeof(double) * lbm::kPartialStride) != hipSuccess ||
         hipHostMalloc(&c->red_host, sizeof(double) * lbm::kPartialStride, hipHostMallocDefault) != hipSuccess)
         return bail(fail(c, LBM_ENOMEM, "cannot allocate the link mask, index or reduction buffers"));
@@ -546,7 +630,22 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         if (hipMemcpy(c->wstart, ws.data(), sizeof(int32_t) * ws.size(), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(c->wpos, wp.data(), sizeof(uint16_t) * wp.size(), hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(c, LBM_EDEVICE, "cannot upload the work lists"));
+        if (p.zchunk == 0) {   // default z-chunks: balanced work items
+            const int64_t resident =
+                (int64_t)std::max(lbm::step_blocks_per_cu(p.prec, c->tile_x, c->tile_y), 1) * device_cus();
+            std::vector<int32_t> items = balance_items(ws, c->ntx, c->nty, p.nz, c->tile_x, c->tile_y, resident);
+            c->nblk = (int)(items.size() / 4);
+            if (hipMalloc(&c->btab, sizeof(int32_t) * items.size()) != hipSuccess)
+                return bail(fail(c, LBM_ENOMEM, "cannot allocate the work items"));
+            if (hipMemcpy(c->btab, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice) != hipSuccess)
+                return bail(fail(c, LBM_EDEVICE, "cannot upload the work items"));
+        }
     }
+    // Partial sums of the checks: one slot per block of the step, or of a
+    // batch (uniform chunks), whichever is more.
+    if (hipMalloc(&c->partials, sizeof(double) * lbm::kPartialStride *
+                                    std::max<int64_t>(nblocks(c), (int64_t)c->ntx * c->nty * c->nzc)) != hipSuccess)
+        return bail(fail(c, LBM_ENOMEM, "cannot allocate the reduction buffers"));
 
     // Solid mask -> link mask.
     uint8_t *solid_d = nullptr;
@@ -917,7 +1016,7 @@ int lbm_info(const lbm_ctx *c, lbm_info_t *out) {
     out->bytes_per_lu = (int32_t)(2 * 2 * 19 * c->esz);
     out->tile_x = c->tile_x;
     out->tile_y = c->tile_y;
-    out->zchunk = c->zchunk;
+    out->zchunk = c->btab ? 0 : c->zchunk;   // 0: balanced work items of varying depth
     out->blocks = nblocks(c);
     out->mass0[0] = c->mass0[0];
     out->mass0[1] = c->mass0[1];
@@ -1015,8 +1114,9 @@ int upload_descs(lbm_batch *b) {
     for (size_t d = 0; d < b->ctx.size(); ++d) {
         lbm_ctx *c = b->ctx[d];
         lbm::StepLaunch L = make_launch(c, c->f[c->cur], c->f[1 - c->cur]);
-        L.zchunk = b->zchunk[d];
+        L.zchunk = b->zchunk[d];   // a batch cuts every domain into uniform chunks
         L.nzc = b->nzc[d];
+        L.btab = nullptr;
         lbm::fill_batch_desc(b->prec, L, b->descs_host.data() + d * b->desc_size);
     }
     if (hipMemcpyAsync(b->descs_dev, b->descs_host.data(), b->descs_host.size(), hipMemcpyHostToDevice, b->stream) !=

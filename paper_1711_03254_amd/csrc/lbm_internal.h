@@ -47,6 +47,11 @@ struct StepLaunch {
     int64_t ngroups;        // slot groups per buffer half (fluid sites' groups plus padding)
     int tile_x, tile_y, zchunk;
     int ntx, nty, nzc;      // tiles in x, y and chunks in z
+    // Work items of the launch, 4 ints each (tile x, tile y, first and end
+    // plane), one per block; null: every column cut into chunks of zchunk
+    // planes (ntx nty nzc blocks)
+    const int32_t *btab;
+    int nblk;
     double tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
     double tau_crit;        // 32/16-bit storage: sites with tau_mix below it form P_ab in FP64
     int eq_kind, force_kind, wall_kind;

@@ -116,6 +116,7 @@ struct KArgs {
     const int32_t *wstart;  // work list bounds per tile column and plane
     const uint16_t *wpos;   // work list entries: tile positions of the fluid sites
     int nx, ny, nz, ntx, nty, zchunk;
+    const int32_t *btab;    // per block: tile x, tile y, first and end plane (null: uniform z-chunks)
     uint32_t half_bytes;    // bytes of one buffer half (directions 0-10 or 11-18)
     C tau0, tau1, G, gx, gy, gz, wall0, wall1, ref0, ref1;
     C tau_crit;             // sites with tau_mix below it form P_ab in FP64 (32/16-bit storage)
@@ -458,9 +459,9 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
     return b < (per << 3) ? (b & 7) * per + (b >> 3) : b;
 }
 
-// One block's work: the tile with linear index b = tx + ntx (ty + nty zc) of
-// the domain described by a; partial sums (MODE_CHECK / MODE_MOMENTS) go to
-// a.partials[slot].
+// One block's work: work item b of the domain described by a (a tile
+// column and a range of z planes, block_item); partial sums (MODE_CHECK /
+// MODE_MOMENTS) go to a.partials[slot].
 //
 // Per plane: the tile's fluid sites are taken from the plane's work list
 // (lane j gets the j-th fluid site, so lanes are busy only where there is
@@ -469,6 +470,26 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
 // moments per component of its site (the regularized collision rebuilds f*
 // from them and the force), the ring only its densities.  The collision of
 // a plane waits for the next plane's densities (one barrier per plane).
+// The tile column and z-range of work item b: from the launch's table of
+// balanced items (uniform reads through the scalar unit), else column
+// b mod (ntx nty), chunk of zchunk planes b / (ntx nty).
+template <typename S>
+__device__ __forceinline__ void block_item(const KArgs<S> &a, int b, int &tx, int &ty, int &z0, int &z1) {
+    if (a.btab) {
+        const cint32 *t = (const cint32 *)(a.btab + 4 * b);
+        tx = t[0];
+        ty = t[1];
+        z0 = t[2];
+        z1 = t[3];
+    } else {
+        tx = b % a.ntx;
+        b /= a.ntx;
+        ty = b % a.nty;
+        z0 = (b / a.nty) * a.zchunk;
+        z1 = min(z0 + a.zchunk, a.nz);
+    }
+}
+
 template <typename S, int TX, int TY, int MODE>
 __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     using C = typename Codec<S>::C;
@@ -487,12 +508,8 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     __shared__ int kid[6][HH][HW];
     __shared__ double red[NT / 64][6];
 
-    const int tx = b % a.ntx;
-    b /= a.ntx;
-    const int ty = b % a.nty;
-    const int zc = b / a.nty;
-    const int z0 = zc * a.zchunk;
-    const int z1 = min(z0 + a.zchunk, a.nz);
+    int tx, ty, z0, z1;
+    block_item(a, b, tx, ty, z0, z1);
 
     const int tid = threadIdx.x;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -1004,12 +1021,8 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
     // the plane to collide (written by the lane itself one plane earlier)
     __shared__ float mom[15][NT];
 
-    const int tx = b % a.ntx;
-    b /= a.ntx;
-    const int ty = b % a.nty;
-    const int zc = b / a.nty;
-    const int z0 = zc * a.zchunk;
-    const int z1 = min(z0 + a.zchunk, a.nz);
+    int tx, ty, z0, z1;
+    block_item(a, b, tx, ty, z0, z1);
 
     const int tid = threadIdx.x;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -1771,6 +1784,7 @@ KArgs<S> make_kargs(const StepLaunch &L) {
     a.wpos = L.wpos;
     a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
     a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk;
+    a.btab = L.btab;
     a.half_bytes = (uint32_t)(L.ngroups * kHalfDirs * kGroup * 2 * (int64_t)sizeof(S));
     a.tau0 = (C)L.tau0; a.tau1 = (C)L.tau1; a.G = (C)L.G;
     a.gx = (C)L.gx; a.gy = (C)L.gy; a.gz = (C)L.gz;
@@ -1786,7 +1800,7 @@ KArgs<S> make_kargs(const StepLaunch &L) {
 template <typename S, int TX, int TY>
 hipError_t launch_typed(Mode mode, const StepLaunch &L, hipStream_t s) {
     const KArgs<S> a = make_kargs<S>(L);
-    const dim3 grid((unsigned)(L.ntx * L.nty * L.nzc)), block(TX * TY);
+    const dim3 grid((unsigned)(L.btab ? L.nblk : L.ntx * L.nty * L.nzc)), block(TX * TY);
     const bool hi = sizeof(S) < 8 && L.tau_crit > 0;
     switch (mode) {
     case MODE_STEP:
