@@ -191,3 +191,34 @@ def test_warm_start_end_to_end():
            factors={p: r[p]["factors"] for p in ("fp32", "fp16s")},
            reached={p: {a: r[p][a]["reached"][0] for a in ("cold", "warm")} for p in ("fp32", "fp16s")},
            final={p: {a: r[p][a]["final"] for a in ("cold", "warm")} for p in ("fp32", "fp16s")})
+
+
+def test_trained_surrogate_shortens_the_solve_at_128():
+    """What the committed surrogate gains over the method without it, on a
+    held-out 128^3 coupled subvolume (seed 10100, not among the training
+    seeds): steps to the accuracy target (4e-2 in u_F, 4e-3 in rho_A against
+    100 000 cold FP64 steps) from the cold start and from the warm start, at
+    FP32 and FP16S storage.  Asserted: the warm start reaches the target in
+    fewer steps at both (measured with the 200 000-step reference: 500
+    against 2500 at FP32, 500 against 6000 at FP16S), and the prediction is
+    closer to the reference than the cold state in both fields."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1711_03254_amd import inputs, lbm, surrogate, warmstart as ws
+    lbm.load_library()
+    here = os.path.dirname(os.path.abspath(__file__))
+    net = surrogate.Surrogate.load(os.path.join(here, "..", "paper_1711_03254_amd", "weights",
+                                                "surrogate_coupled_128.npz"))
+    phys = ws.physics()
+    solid, ra0, rb0, _ = inputs.mixture_case(128, 10100)
+    ref_a, ref_u, _ = ws.reference(solid, ra0, rb0, phys, 100000)
+    r = ws.compare(net, dict(solid=solid, ra0=ra0, rb0=rb0), phys, (ref_a, ref_u), [(0.04, 0.004)], every=500,
+                   max_steps=20000)
+    steps = {p: {a: (r[p][a]["reached"][0] or {}).get("steps") for a in ("cold", "warm")} for p in ("fp32", "fp16s")}
+    record("warm_start_128", prediction=r["prediction_distance"], cold_start=r["cold_start_distance"], steps=steps,
+           predict_seconds=r["predict_seconds"], factors={p: r[p]["factors"]["warm"] for p in ("fp32", "fp16s")})
+    assert r["prediction_distance"]["u"] < r["cold_start_distance"]["u"]
+    assert r["prediction_distance"]["rho_a"] < r["cold_start_distance"]["rho_a"]
+    for p in ("fp32", "fp16s"):
+        assert steps[p]["cold"] is not None and steps[p]["warm"] is not None, (p, steps)
+        assert steps[p]["warm"] < steps[p]["cold"], (p, steps)
