@@ -492,6 +492,7 @@ __device__ __forceinline__ void block_item(const KArgs<S> &a, int b, int &tx, in
 
 template <typename S, int TX, int TY, int MODE>
 __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
+    static_assert(sizeof(S) == 8, "the 32- and 16-bit storage forms use step_body_pipe");
     using C = typename Codec<S>::C;
     constexpr int NT = TX * TY;
     constexpr int RW = TX + 2, RH = TY + 2;     // density tile with its ring
@@ -518,17 +519,10 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     constexpr uint32_t PB = 2 * sizeof(S);      // bytes of a component pair
     constexpr uint32_t DS = kGroup * PB;        // from one direction's run to the next
 
-    // Ring position j (0 <= j < NR) in index-tile coordinates: the rows
-    // above and below the tile, then its left and right columns.
-    auto ring_pos = [&](int j, int &hr, int &hc) {
-        if (j < RW) { hr = 1; hc = 1 + j; }
-        else if (j < 2 * RW) { hr = RH; hc = 1 + j - RW; }
-        else if (j < 2 * RW + TY) { hr = 2 + j - 2 * RW; hc = 1; }
-        else { hr = 2 + j - 2 * RW - TY; hc = RW; }
-    };
-    // FP64 form: this thread's ring site in density-tile coordinates
-    // (rr, rc); ring index rt counts down from the last thread, so that the
-    // ring falls on the waves the work list leaves idle first.
+    // This thread's ring site in density-tile coordinates (rr, rc): the
+    // rows above and below the tile, then its left and right columns; ring
+    // index rt counts down from the last thread, so that the ring falls on
+    // the waves the work list leaves idle first.
     const int rt = NT - 1 - tid;
     const bool has_ring = rt < NR;
     int rr = 0, rc = 0;
@@ -621,12 +615,8 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     // Pulls plane zw (z0 - 1 <= zw <= z1, unwrapped) into density slot
     // lslot; the interior's moments go to mn.  Index slot of plane p:
     // (p - z0 + 2) mod 6; the tile of plane zw + 2 is staged on the way.
-    //
-    // The plane's pulls form one job list: jobs 0 .. cnt - 1 are the tile's
-    // fluid sites (job j = work-list entry j), jobs cnt .. cnt + NR - 1 the
-    // ring positions; job j runs on lane j mod NT in pass j / NT, so a lane
-    // holds one site's populations at a time and a second pass is needed
-    // only where cnt + NR > NT.
+    // Lane j pulls the plane's j-th fluid site (work-list entry j) and its
+    // own ring position, both in one round trip.
     auto load_plane = [&](int zw, int lslot, bool keep) {
         const int qw = zw - z0 + 2;
         const int qm = (qw + 5) % 6, q0 = qw % 6, qp = (qw + 1) % 6;
@@ -638,71 +628,38 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
         fetch_work(zw + 1, wcnt, wpos);
         fluid_n = tid < cnt;
         pn = pos_here;
-        if constexpr (sizeof(S) == 8) {
-            // FP64: every thread pulls its work-list site and its ring site
-            // in one round trip (no second pass); the job list below gave
-            // run-to-run differences in the batched FP64 step, which this
-            // form does not.
-            const bool fi = tid < cnt;
-            const int si = fi ? kid[q0][ly + 2][lx + 2] : -1;
-            const int sr = has_ring ? kid[q0][rr + 1][rc + 1] : -1;
-            const bool fr = sr >= 0;
-            kn = si;
-            R ri[2][19], rg[2][19];
-            if (fi) issue(ly + 2, lx + 2, qm, q0, qp, (uint32_t)si, ri);
-            if (fr) issue(rr + 1, rc + 1, qm, q0, qp, (uint32_t)sr, rg);
-            __builtin_amdgcn_sched_barrier(0);
-            if (fi) {
-                C r0, r1;
-                if (keep) {
-                    mn[0] = moments_of<S>(ri[0], ref0);
-                    mn[1] = moments_of<S>(ri[1], ref1);
-                    r0 = mn[0].r;
-                    r1 = mn[1].r;
-                } else {
-                    r0 = density_of<S>(ri[0], ref0);
-                    r1 = density_of<S>(ri[1], ref1);
-                }
-                psi[lslot][ly + 1][lx + 1] = PsiPair{r0, r1};
+        // (A job list with a second pass for the ring, as the 32/16-bit
+        // step runs, gave run-to-run differences in the FP64 step with
+        // 512-thread blocks; this form does not.)
+        const bool fi = tid < cnt;
+        const int si = fi ? kid[q0][ly + 2][lx + 2] : -1;
+        const int sr = has_ring ? kid[q0][rr + 1][rc + 1] : -1;
+        const bool fr = sr >= 0;
+        kn = si;
+        R ri[2][19], rg[2][19];
+        if (fi) issue(ly + 2, lx + 2, qm, q0, qp, (uint32_t)si, ri);
+        if (fr) issue(rr + 1, rc + 1, qm, q0, qp, (uint32_t)sr, rg);
+        __builtin_amdgcn_sched_barrier(0);
+        if (fi) {
+            C r0, r1;
+            if (keep) {
+                mn[0] = moments_of<S>(ri[0], ref0);
+                mn[1] = moments_of<S>(ri[1], ref1);
+                r0 = mn[0].r;
+                r1 = mn[1].r;
+            } else {
+                r0 = density_of<S>(ri[0], ref0);
+                r1 = density_of<S>(ri[1], ref1);
             }
-            if (has_ring) {
-                C q0v = a.wall0, q1v = a.wall1;
-                if (fr) {
-                    q0v = density_of<S>(rg[0], ref0);
-                    q1v = density_of<S>(rg[1], ref1);
-                }
-                psi[lslot][rr][rc] = PsiPair{q0v, q1v};
+            psi[lslot][ly + 1][lx + 1] = PsiPair{r0, r1};
+        }
+        if (has_ring) {
+            C q0v = a.wall0, q1v = a.wall1;
+            if (fr) {
+                q0v = density_of<S>(rg[0], ref0);
+                q1v = density_of<S>(rg[1], ref1);
             }
-        } else
-        for (int pass = 0; pass * NT < cnt + NR; ++pass) {
-            const int j = tid + pass * NT;
-            const bool site = j < cnt;
-            const bool ring = !site && j - cnt < NR;
-            int hr = ly + 2, hc = lx + 2;
-            if (!site) ring_pos(j - cnt, hr, hc);
-            const int self = site || ring ? kid[q0][hr][hc] : -1;
-            if (site) kn = self;
-            R raw[2][19];
-            // All of the job's loads are issued before any is consumed: one
-            // memory round trip per pass.  Lanes without a fluid job issue
-            // no load and use none of these values.
-            if (self >= 0) issue(hr, hc, qm, q0, qp, (uint32_t)self, raw);
-            __builtin_amdgcn_sched_barrier(0);
-            C r0 = a.wall0, r1 = a.wall1;
-            if (self >= 0) {
-                if (site && keep) {
-                    mn[0] = moments_of<S>(raw[0], ref0);
-                    mn[1] = moments_of<S>(raw[1], ref1);
-                    r0 = mn[0].r;
-                    r1 = mn[1].r;
-                } else {
-                    r0 = density_of<S>(raw[0], ref0);
-                    r1 = density_of<S>(raw[1], ref1);
-                }
-            }
-            if (site || ring) {
-                psi[lslot][hr - 1][hc - 1] = PsiPair{r0, r1};
-            }
+            psi[lslot][rr][rc] = PsiPair{q0v, q1v};
         }
         if (kid[q0][tly + 2][tlx + 2] < 0) {   // solid site of the tile: the wall densities
             psi[lslot][tly + 1][tlx + 1] = PsiPair{a.wall0, a.wall1};
