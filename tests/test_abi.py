@@ -128,6 +128,31 @@ def test_init_rejects_bad_parameters_on_the_host(lbm, bad, needle):
     assert needle in str(ei.value)
 
 
+def test_warm_start_calls_reject_null_arguments_on_the_host(lbm):
+    """The restart, residual and distance entry points and the surrogate's
+    feature / decoding kernels return LBM_EINVAL for NULL or bad arguments
+    before any device work (no GPU needed)."""
+    import ctypes
+    from paper_1711_03254_amd import nn
+    lib = nn.load()   # argument types of every call
+    out = (ctypes.c_double * 2)()
+    p = ctypes.c_void_p(8)
+    assert lib.lbm_set_fields_strain(None, p, p, p, 0) == lbm.LBM_EINVAL
+    assert lib.lbm_residual(None, out) == lbm.LBM_EINVAL
+    assert lib.lbm_distance(None, p, p, 0, out) == lbm.LBM_EINVAL
+    assert lib.nn_solid_distance(None, p, p, 4, 4, 4, 2, None) == lbm.LBM_EINVAL
+    assert lib.nn_solid_distance(p, p, p, 4, 4, 4, 0, None) == lbm.LBM_EINVAL          # radius < 1
+    assert lib.nn_features(p, p, p, p, ctypes.c_float(8.0), p, 16, 2, 64, None) == lbm.LBM_EINVAL   # c < 3
+    assert lib.nn_features(p, p, p, p, ctypes.c_float(0.0), p, 16, 16, 64, None) == lbm.LBM_EINVAL  # scale
+    dbl = ctypes.c_double
+    assert lib.nn_decode_fields(p, 4, p, p, p, dbl(0.1), dbl(0.1), dbl(1e-5), ctypes.c_float(1.0),
+                                ctypes.c_float(1.0), dbl(1e-3), p, p, p, p, 64, None) == lbm.LBM_EINVAL   # ldo < 5
+    assert lib.nn_decode_fields(p, 16, p, p, p, dbl(0.0), dbl(0.1), dbl(1e-5), ctypes.c_float(1.0),
+                                ctypes.c_float(1.0), dbl(1e-3), p, p, p, p, 64, None) == lbm.LBM_EINVAL   # nu_a
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_set_fields_strain(None, None, None, None)   # no velocity field
+
+
 def test_init_rejects_oversized_plane(lbm):
     import numpy as np
     r = np.ones(1)
