@@ -106,6 +106,34 @@ def test_strain_start_is_near_steady(prec):
     assert change[True] < 0.2 * change[False]
 
 
+@pytest.mark.parametrize("wall_kind,rho_s", [(0, 0.0), (0, 0.3), (1, -0.3)])
+def test_restart_gives_back_its_velocity(wall_kind, rho_s):
+    """lbm_set_fields_strain takes u_F of Eq. (8): the populations it sets
+    carry each component's momentum rho_a u_F - F_a / 2 with F_a from its own
+    force routine, so lbm_moments, which forms u_F = (j + F / 2) / rho with
+    the step's force, must give u_F back to rounding -- with solids, a wall
+    potential of either sign, both wall forms, coupling and gravity (the
+    strain part carries no momentum, and the equilibrium's third-order
+    terms none either on D3Q19)."""
+    from paper_1711_03254_amd import inputs, lbm
+    lbm.load_library()
+    shape = (12, 16, 20)
+    rng = np.random.default_rng(40 + wall_kind)
+    solid = inputs.random_mask(shape, 0.2, 41)
+    ra = np.where(solid == 1, 0.0, inputs.smooth_random_density(shape, 42, mean=0.7, amp=0.1))
+    rb = np.where(solid == 1, 0.0, inputs.smooth_random_density(shape, 43, mean=0.3, amp=0.1))
+    u = np.where(solid[None] == 1, 0.0, rng.normal(scale=1e-3, size=(3,) + shape))
+    ctx = lbm.lbm_init(lbm.Params(shape[2], shape[1], shape[0], prec=lbm.LBM_FP64, tau=(0.7, 1.2), G=-1.5,
+                                  g=(1e-5, -2e-5, 3e-5), rho_s=rho_s, wall_kind=wall_kind, solid=solid,
+                                  rho_init=(ra, rb)))
+    lbm.lbm_set_fields_strain(ctx, ra, rb, u)
+    ga, gb, gu = lbm.lbm_moments(ctx)
+    lbm.lbm_free(ctx)
+    np.testing.assert_allclose(ga, ra, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(gb, rb, rtol=1e-13, atol=1e-15)
+    assert np.abs(gu - u).max() <= 1e-12 * np.abs(u).max()
+
+
 def test_residual_matches_the_fields():
     """lbm_residual against the same norms taken on the host from
     lbm_moments, on a coupled mixture in a porous subvolume."""
