@@ -153,6 +153,12 @@ __host__ __device__ constexpr uint32_t group_off(uint32_t k, uint32_t pb) {
 __host__ __device__ constexpr uint32_t dir_off(int i, uint32_t pb) {
     return (uint32_t)(i < kSplit ? i : i - kSplit) * (uint32_t)kGroup * pb;
 }
+// Index tiles hold group_off of each site as a 32-bit pattern and this value
+// where the site is solid: all bits set, which no offset takes (offsets are
+// multiples of the pair size and a half stays below 4 GiB).  Offsets of 2 GiB
+// and more read as negative ints, so a site is solid exactly when its entry
+// equals kSolidOff, never when it is merely negative.
+constexpr int kSolidOff = -1;
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -505,7 +511,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     // moves a neighbour's pair.
     struct alignas(2 * sizeof(C)) PsiPair { C a, b; };
     __shared__ PsiPair psi[4][RH][RW];
-    // byte offset (group_off) of each site's population pairs, -1 where solid
+    // byte offset (group_off) of each site's population pairs, kSolidOff where solid
     __shared__ int kid[6][HH][HW];
     __shared__ double red[NT / 64][6];
 
@@ -571,7 +577,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
     auto store_idx = [&](int q, const int (&v)[NE]) {
 #pragma unroll
         for (int j = 0; j < NE; ++j)
-            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? (int)group_off((uint32_t)v[j], PB) : -1;
+            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? (int)group_off((uint32_t)v[j], PB) : kSolidOff;
     };
 
     const __amdgpu_buffer_rsrc_t srcA = half_rsrc(a.src, 0, hb), srcB = half_rsrc(a.src, 1, hb);
@@ -595,8 +601,8 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                 constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
                 const int q = Z == 0 ? q0 : (Z > 0 ? qm : qp);   // plane zw - Z
                 const int nb = kid[q][hr - Y][hc - X];
-                if constexpr (i == lo) off = nb >= 0 ? (uint32_t)nb : self_p;
-                else off = nb >= 0 ? (uint32_t)nb + DS : self;
+                if constexpr (i == lo) off = nb != kSolidOff ? (uint32_t)nb : self_p;
+                else off = nb != kSolidOff ? (uint32_t)nb + DS : self;
             }
             pair_load<S>(lo < kSplit ? srcA : srcB, off, soff, raw[0][i], raw[1][i]);
         });
@@ -632,9 +638,9 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
         // step runs, gave run-to-run differences in the FP64 step with
         // 512-thread blocks; this form does not.)
         const bool fi = tid < cnt;
-        const int si = fi ? kid[q0][ly + 2][lx + 2] : -1;
-        const int sr = has_ring ? kid[q0][rr + 1][rc + 1] : -1;
-        const bool fr = sr >= 0;
+        const int si = fi ? kid[q0][ly + 2][lx + 2] : kSolidOff;
+        const int sr = has_ring ? kid[q0][rr + 1][rc + 1] : kSolidOff;
+        const bool fr = sr != kSolidOff;
         kn = si;
         R ri[2][19], rg[2][19];
         if (fi) issue(ly + 2, lx + 2, qm, q0, qp, (uint32_t)si, ri);
@@ -661,7 +667,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
             }
             psi[lslot][rr][rc] = PsiPair{q0v, q1v};
         }
-        if (kid[q0][tly + 2][tlx + 2] < 0) {   // solid site of the tile: the wall densities
+        if (kid[q0][tly + 2][tlx + 2] == kSolidOff) {   // solid site of the tile: the wall densities
             psi[lslot][tly + 1][tlx + 1] = PsiPair{a.wall0, a.wall1};
         }
         store_idx((qw + 2) % 6, vnext);
@@ -736,7 +742,7 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
                     if constexpr (i > 0) {
                         constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
                         const int q = ((z + Z) - z0 + 2) % 6;   // index slot of plane z + Z
-                        const C sol = kid[q][ly + 2 + Y][lx + 2 + X] < 0 ? C(w_of(i)) : C(0);
+                        const C sol = kid[q][ly + 2 + Y][lx + 2 + X] == kSolidOff ? C(w_of(i)) : C(0);
                         if constexpr (X != 0) Sx += C(X) * sol;
                         if constexpr (Y != 0) Sy += C(Y) * sol;
                         if constexpr (Z != 0) Sz += C(Z) * sol;
@@ -1037,7 +1043,7 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
         const int q = kslot(p);
 #pragma unroll
         for (int j = 0; j < NE; ++j)
-            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? (int)group_off((uint32_t)v[j], PB) : -1;
+            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? (int)group_off((uint32_t)v[j], PB) : kSolidOff;
     };
     auto psi_slot = [&](int p) { return (p - z0 + 1) & 3; };   // density slot of plane p >= z0 - 1
 
@@ -1062,8 +1068,8 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
                 constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
                 const int q = Z == 0 ? q0 : (Z > 0 ? qm : qp);   // plane zw - Z
                 const int nb = kid[q][hr - Y][hc - X];
-                if constexpr (i == lo) off = nb >= 0 ? (uint32_t)nb : self_p;
-                else off = nb >= 0 ? (uint32_t)nb + DS : self;
+                if constexpr (i == lo) off = nb != kSolidOff ? (uint32_t)nb : self_p;
+                else off = nb != kSolidOff ? (uint32_t)nb + DS : self;
             }
             raw[i] = held_load<S>(lo < kSplit ? srcA : srcB, off, soff);
         });
@@ -1076,7 +1082,7 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
     auto consume = [&](int zw, bool is_site, bool is_job, int hr, int hc, int self, const H (&raw)[19],
                        bool want_mom, SiteMoments &sm) {
         C r0 = a.wall0, r1 = a.wall1;
-        if (self >= 0) {
+        if (self != kSolidOff) {
             if (is_site && want_mom) {
                 Moments<C> m0, m1;
                 held_density_momentum<S, 0>(raw, ref0, m0);
@@ -1113,14 +1119,14 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
             const int j = tid + pass * NT;
             int hr = 0, hc = 0;
             const bool is_job = job_at(j, cnt, 0, hr, hc);
-            const int self = is_job ? kid[kslot(zw)][hr][hc] : -1;
+            const int self = is_job ? kid[kslot(zw)][hr][hc] : kSolidOff;
             H raw[19];
-            if (self >= 0) issue(zw, hr, hc, (uint32_t)self, raw);
+            if (self != kSolidOff) issue(zw, hr, hc, (uint32_t)self, raw);
             __builtin_amdgcn_sched_barrier(0);
             SiteMoments unused;
             consume(zw, false, is_job, hr, hc, self, raw, false, unused);
         }
-        if (kid[kslot(zw)][tly + 2][tlx + 2] < 0)   // solid site of the tile: the wall densities
+        if (kid[kslot(zw)][tly + 2][tlx + 2] == kSolidOff)   // solid site of the tile: the wall densities
             psi[psi_slot(zw)][tly + 1][tlx + 1] = PsiPair{a.wall0, a.wall1};
     };
 
@@ -1159,8 +1165,8 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
         mc = SiteMoments{C(0), C(0), C(0), {zm, zm}};
         mn = mc;
     }
-    int kc = -1, pc = 0;   // the site job of the plane to collide: byte offset (-1: none), tile position
-    int kn = -1, pn = 0;   // ... of the next plane
+    int kc = kSolidOff, pc = 0;   // the site job of the plane to collide: byte offset (kSolidOff: none), tile position
+    int kn = kSolidOff, pn = 0;   // ... of the next plane
 
     // ---- prologue: index tiles of planes z0 - 2 .. z0 + 3; planes z0 - 1,
     // z0 and z0 + 1 pulled, one round trip each.
@@ -1180,15 +1186,15 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
         const int pos = entry(bd);
         int hr = 0, hc = 0;
         const bool is_job = job_at(tid, bd.cnt, pos, hr, hc);
-        const int self = is_job ? kid[kslot(zw)][hr][hc] : -1;
+        const int self = is_job ? kid[kslot(zw)][hr][hc] : kSolidOff;
         H raw[19];
-        if (self >= 0) issue(zw, hr, hc, (uint32_t)self, raw);
+        if (self != kSolidOff) issue(zw, hr, hc, (uint32_t)self, raw);
         __builtin_amdgcn_sched_barrier(0);
         const bool is_site = tid < bd.cnt;
         SiteMoments unused;
         consume(zw, is_site, is_job, hr, hc, self, raw, q > 0, q == 1 ? mc : (q == 2 ? mn : unused));
-        if (q == 1) { kc = is_site ? self : -1; pc = pos; }
-        if (q == 2) { kn = is_site ? self : -1; pn = pos; }
+        if (q == 1) { kc = is_site ? self : kSolidOff; pc = pos; }
+        if (q == 2) { kn = is_site ? self : kSolidOff; pn = pos; }
         finish_plane(zw, bd.cnt);
     }
     mom_put(mc);
@@ -1205,7 +1211,7 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
         // D: the pulls of plane z + 2 (the loads go out before this plane's
         // stores)
         H raw[19];
-        int self2 = -1, pos3 = 0;
+        int self2 = kSolidOff, pos3 = 0;
         Bounds b4{0, 0};
         if (more) {
             fetch_idx(z + 4, vnext);
@@ -1213,8 +1219,8 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
             b4 = bounds(z + 4);
             int hr2 = 0, hc2 = 0;
             const bool is_job = job_at(tid, b2.cnt, pos2, hr2, hc2);
-            self2 = is_job ? kid[kslot(z + 2)][hr2][hc2] : -1;
-            if (self2 >= 0) issue(z + 2, hr2, hc2, (uint32_t)self2, raw);
+            self2 = is_job ? kid[kslot(z + 2)][hr2][hc2] : kSolidOff;
+            if (self2 != kSolidOff) issue(z + 2, hr2, hc2, (uint32_t)self2, raw);
         }
         __builtin_amdgcn_sched_barrier(0);
 
@@ -1222,7 +1228,7 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
         const int sm_ = psi_slot(z - 1), s0 = psi_slot(z), sp = psi_slot(z + 1);
         const int lx = pc % TX, ly = pc / TX;
         const bool inside = tx * TX + lx < nx && ty * TY + ly < ny;   // not a periodic image
-        const bool collide = inside && kc >= 0;
+        const bool collide = inside && kc != kSolidOff;
         if (collide) {
             mom_get(mc);
             const PsiPair here = psi[s0][ly + 1][lx + 1];
@@ -1261,7 +1267,7 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
                     constexpr int i = I;
                     if constexpr (i > 0) {
                         constexpr int X = cx_of(i), Y = cy_of(i), Z = cz_of(i);
-                        const C sol = kid[kslot(z + Z)][ly + 2 + Y][lx + 2 + X] < 0 ? C(w_of(i)) : C(0);
+                        const C sol = kid[kslot(z + Z)][ly + 2 + Y][lx + 2 + X] == kSolidOff ? C(w_of(i)) : C(0);
                         if constexpr (X != 0) Sx += C(X) * sol;
                         if constexpr (Y != 0) Sy += C(Y) * sol;
                         if constexpr (Z != 0) Sz += C(Z) * sol;
@@ -1321,7 +1327,7 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
             int hra = 0, hca = 0;
             const bool is_job = job_at(tid, b2.cnt, pos2, hra, hca);
             consume(z + 2, is_site, is_job, hra, hca, self2, raw, true, mn);
-            kn = is_site ? self2 : -1;
+            kn = is_site ? self2 : kSolidOff;
             pn = pos2;
             finish_plane(z + 2, b2.cnt);
             store_idx(z + 4, vnext);

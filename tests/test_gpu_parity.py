@@ -463,6 +463,59 @@ def test_full_size_sampled_sites(lbm, ora, packed_spheres, prec):
     del fd
 
 
+@pytest.mark.parametrize("prec,nz,zfar", [("fp64", 192, 188), ("fp32", 384, 376)])
+def test_population_offsets_beyond_2_gib(lbm, ora, prec, nz, zfar):
+    """A half of the population storage may reach 4 GiB, so byte offsets
+    within a half of 2 GiB and more (negative as 32-bit ints) must address
+    fluid sites like any other.  A 256 x 256 x nz lattice, fluid but for a
+    wall row, one step from a seeded random state at the default launch
+    shape: FP64 runs the single-pass step, FP32 the pipelined one that the
+    16-bit forms share.  2000 sites of planes >= zfar (all of whose offsets
+    are past 2 GiB), 500 next to the wall and 500 anywhere are recomputed by
+    the oracle (FP64 to 1e-12, FP32 to 1e-5)."""
+    import torch
+    ny = nx = 256
+    shape = (nz, ny, nx)
+    solid = np.zeros(shape, np.uint8)
+    solid[:, 0, :] = 1
+    n = solid.size
+    rA = (0.7 + 0.1 * inputs.uniform(301, n)).reshape(shape)
+    rB = (0.3 + 0.1 * inputs.uniform(302, n)).reshape(shape)
+    rA[solid == 1] = 0
+    rB[solid == 1] = 0
+    phys = dict(tau=(0.8, 1.2), G=-1.0, g=(0.0, 0.0, 1e-5), rho_s=0.2)
+    # Sites are numbered plane by plane, so a site of plane z has slot
+    # k >= (fluid sites of the planes below); its offset in its half is at
+    # least (11 k - 352) pair sizes (11 direction runs of 32 pairs a group).
+    pb = {"fp64": 16, "fp32": 8}[prec]
+    k_min = zfar * nx * (ny - 1)
+    assert (11 * k_min - 352) * pb >= 2 ** 31
+    ctx = lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(rA, rB),
+                                  check_every=0, **phys))
+    p = ora.Params(nx, ny, nz, solid=solid, **phys)
+    plane = nx * ny
+    far = zfar * plane + (inputs.uniform(303, 2000) * ((nz - zfar) * plane)).astype(np.int64)
+    wall = (inputs.uniform(304, 500) * nz).astype(np.int64) * plane + nx + \
+        (inputs.uniform(305, 500) * nx).astype(np.int64)
+    anyw = (inputs.uniform(306, 500) * n).astype(np.int64)
+    far = far[solid.ravel()[far] == 0]
+    pick = np.concatenate([far, anyw[solid.ravel()[anyw] == 0], wall])
+    f0 = ora.init(p, rA, rB)
+    lbm.lbm_step(ctx, 1)
+    fd = torch.empty((2, 19) + shape, dtype=torch.float64, device="cuda")
+    lbm.lbm_get_populations(ctx, fd)
+    got = fd.view(2, 19, -1)[:, :, torch.from_numpy(pick).cuda()].permute(2, 0, 1).cpu().numpy()
+    del fd
+    want = ora.step_sites(p, f0, pick)
+    del f0
+    dev = nmax(got, want)
+    dev_far = nmax(got[:len(far)], want[:len(far)])
+    record("offsets_beyond_2gib", prec=prec, shape=list(shape), tile=list(lbm.lbm_info(ctx)["tile"]), dev=dev,
+           dev_far=dev_far, sites=int(len(pick)))
+    lbm.lbm_free(ctx)
+    assert dev <= TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s", "bf16s"])
 def test_resume_into_placeholder_context(lbm, prec):
     """A checkpoint resumed into a context created from placeholder fields
