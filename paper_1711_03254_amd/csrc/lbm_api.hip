@@ -23,6 +23,7 @@ struct lbm_ctx {
     int cur = 0;
     uint32_t *links = nullptr;   // per-site link mask (set-up and exchange kernels)
     int32_t *idx = nullptr;      // compact population index per site, -1 where solid
+    int32_t *itab = nullptr;     // index tiles of the step for the context's tile shape
     int32_t *wstart = nullptr;   // work lists of the step: bounds per tile column and plane
     int32_t *btab = nullptr;     // balanced work items of the step (4 ints each), or null
     int nblk = 0;                // their number
@@ -268,6 +269,7 @@ lbm::StepLaunch make_launch(const lbm_ctx *c, const void *src, void *dst) {
     L.src = src;
     L.dst = dst;
     L.idx = c->idx;
+    L.itab = c->itab;
     L.wstart = c->wstart;
     L.wpos = c->wpos;
     L.nx = p.nx; L.ny = p.ny; L.nz = p.nz;
@@ -496,7 +498,7 @@ void release(lbm_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (void *q : {c->f[0], c->f[1], (void *)c->links, (void *)c->idx, (void *)c->wstart, (void *)c->btab, (void *)c->wpos,
+    for (void *q : {c->f[0], c->f[1], (void *)c->links, (void *)c->idx, (void *)c->itab, (void *)c->wstart, (void *)c->btab, (void *)c->wpos,
                     (void *)c->partials, (void *)c->red_dev, (void *)c->stage, (void *)c->snap})
         if (q) (void)hipFree(q);
     if (c->red_host) (void)hipHostFree(c->red_host);
@@ -620,6 +622,20 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         return bail(fail(c, LBM_ENOMEM, "cannot allocate the link mask, index or reduction buffers"));
     if (hipMemcpy(c->idx, idx_h.data(), sizeof(int32_t) * c->N, hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(c, LBM_EDEVICE, "cannot upload the site index"));
+    {
+        // The step reads a tile column's index tiles with 32-bit offsets.
+        const int64_t per = (int64_t)(c->tile_x + 4) * (c->tile_y + 4);
+        if ((uint64_t)p.nz * (uint64_t)per * 4u >= (1ull << 32))
+            return bail(fail(c, LBM_EINVAL, "lattice too long in z for the step's index tiles"));
+        const size_t ib = sizeof(int32_t) * (size_t)c->ntx * c->nty * p.nz * per;
+        if (hipMalloc(&c->itab, ib) != hipSuccess) {
+            c->itab = nullptr;
+            return bail(fail(c, LBM_ENOMEM, "cannot allocate the index tiles"));
+        }
+        hipError_t e = lbm::launch_index_tiles(c->idx, c->itab, p.nx, p.ny, p.nz, c->tile_x, c->tile_y,
+                                               (int)(2 * esz), c->stream);
+        if (e != hipSuccess) return bail(fail(c, LBM_EDEVICE, std::string("index tiles: ") + hipGetErrorString(e)));
+    }
     {
         std::vector<int32_t> ws;
         std::vector<uint16_t> wp;

@@ -41,6 +41,7 @@ struct StepLaunch {
     const void *src;
     void *dst;
     const int32_t *idx;     // compact population index of each lattice site, -1 where solid
+    const int32_t *itab;    // index tiles of the step (launch_index_tiles) for this tile shape
     const int32_t *wstart;  // work list bounds: per tile column (ty ntx + tx) nz + 1 entries
     const uint16_t *wpos;   // work list entries: tile positions ly tile_x + lx of fluid sites
     int nx, ny, nz;
@@ -63,6 +64,13 @@ struct StepLaunch {
 hipError_t launch_step(int prec, Mode mode, const StepLaunch &L, hipStream_t s);
 // Sums nblocks partials (fixed order) into out[kPartialStride] on the device.
 hipError_t launch_finalize(const double *partials, int nblocks, double *out, hipStream_t s);
+// Index tiles of the step for tiles of tx x ty sites: per tile column
+// (ty ntx + tx) and plane, the (tx + 4)(ty + 4) sites around the tile (a
+// periodic ring of two) row by row, each as the byte offset of its
+// population pairs (pair_bytes each) within a buffer half, all bits set
+// where solid; ntx nty nz (tx + 4)(ty + 4) entries.
+hipError_t launch_index_tiles(const int32_t *idx, int32_t *itab, int nx, int ny, int nz, int tx, int ty, int pair_bytes,
+                              hipStream_t s);
 // Per-site link mask: bit 0 = site solid, bit i = site - c_i solid (periodic).
 hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, int nz, hipStream_t s);
 // Internal state from fields: f*_j(x) = f_j(x + c_j) if that site is fluid,

@@ -113,6 +113,7 @@ struct KArgs {
     const S *src;
     S *dst;
     const int32_t *idx;     // compact index of each lattice site, -1 where solid
+    const int32_t *itab;    // index tiles of the step per tile column and plane (index_tiles_kernel)
     const int32_t *wstart;  // work list bounds per tile column and plane
     const uint16_t *wpos;   // work list entries: tile positions of the fluid sites
     int nx, ny, nz, ntx, nty, zchunk;
@@ -554,30 +555,25 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
         pos = tid < cnt ? (int)a.wpos[w0 + tid] : 0;
     };
 
-    // The index-tile entries this thread stages: their lattice (x, y).
-    uint32_t exy[NE];
-    bool eok[NE];
-#pragma unroll
-    for (int j = 0; j < NE; ++j) {
-        const int e = tid + j * NT;
-        eok[j] = e < HW * HH;
-        const int er = e / HW, ec = e % HW;
-        exy[j] = (uint32_t)wrap(tx * TX - 2 + ec, nx) + (uint32_t)nx * (uint32_t)wrap(ty * TY - 2 + er, ny);
-    }
+    // This tile column's index tiles (index_tiles_kernel): HW HH entries per
+    // plane, planes in order; entry e of a plane is staged by thread e mod NT.
+    constexpr uint32_t TB = 4u * (uint32_t)(HW * HH);   // bytes of one plane's index tile
     const __amdgpu_buffer_rsrc_t ridx = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<int32_t *>(a.idx), 0, (int)(4u * (uint32_t)a.n_sites), kRsrcWord3);
+        const_cast<int32_t *>(a.itab + (size_t)(ty * a.ntx + tx) * (size_t)nz * (HW * HH)), 0,
+        (int)(TB * (uint32_t)nz), kRsrcWord3);
+    auto eok = [&](int j) { return (j + 1) * NT <= HW * HH || tid + j * NT < HW * HH; };
     auto fetch_idx = [&](int zq, int (&v)[NE]) {
-        const uint32_t zo = (uint32_t)wrap(zq, nz) * nxy * 4u;
+        const uint32_t zo = (uint32_t)wrap(zq, nz) * TB;
 #pragma unroll
         for (int j = 0; j < NE; ++j) {
-            v[j] = -1;
-            if (eok[j]) v[j] = (int)__builtin_amdgcn_raw_buffer_load_b32(ridx, exy[j] * 4u, zo, 0);
+            v[j] = kSolidOff;
+            if (eok(j)) v[j] = (int)__builtin_amdgcn_raw_buffer_load_b32(ridx, 4u * (uint32_t)(tid + j * NT), zo, 0);
         }
     };
     auto store_idx = [&](int q, const int (&v)[NE]) {
 #pragma unroll
         for (int j = 0; j < NE; ++j)
-            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? (int)group_off((uint32_t)v[j], PB) : kSolidOff;
+            if (eok(j)) (&kid[q][0][0])[tid + j * NT] = v[j];
     };
 
     const __amdgpu_buffer_rsrc_t srcA = half_rsrc(a.src, 0, hb), srcB = half_rsrc(a.src, 1, hb);
@@ -1019,23 +1015,19 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
     };
     auto entry = [&](Bounds bd) { return tid < bd.cnt ? (int)a.wpos[bd.w0 + tid] : 0; };
 
-    uint32_t exy[NE];   // lattice (x, y) of the index-tile entries this thread stages
-    bool eok[NE];
-#pragma unroll
-    for (int j = 0; j < NE; ++j) {
-        const int e = tid + j * NT;
-        eok[j] = e < HW * HH;
-        const int er = e / HW, ec = e % HW;
-        exy[j] = (uint32_t)wrap(tx * TX - 2 + ec, nx) + (uint32_t)nx * (uint32_t)wrap(ty * TY - 2 + er, ny);
-    }
+    // This tile column's index tiles (index_tiles_kernel): HW HH entries per
+    // plane, planes in order; entry e of a plane is staged by thread e mod NT.
+    constexpr uint32_t TB = 4u * (uint32_t)(HW * HH);   // bytes of one plane's index tile
     const __amdgpu_buffer_rsrc_t ridx = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<int32_t *>(a.idx), 0, (int)(4u * (uint32_t)a.n_sites), kRsrcWord3);
+        const_cast<int32_t *>(a.itab + (size_t)(ty * a.ntx + tx) * (size_t)nz * (HW * HH)), 0,
+        (int)(TB * (uint32_t)nz), kRsrcWord3);
+    auto eok = [&](int j) { return (j + 1) * NT <= HW * HH || tid + j * NT < HW * HH; };
     auto fetch_idx = [&](int zq, int (&v)[NE]) {
-        const uint32_t zo = (uint32_t)wrap(zq, nz) * nxy * 4u;
+        const uint32_t zo = (uint32_t)wrap(zq, nz) * TB;
 #pragma unroll
         for (int j = 0; j < NE; ++j) {
-            v[j] = -1;
-            if (eok[j]) v[j] = (int)__builtin_amdgcn_raw_buffer_load_b32(ridx, exy[j] * 4u, zo, 0);
+            v[j] = kSolidOff;
+            if (eok(j)) v[j] = (int)__builtin_amdgcn_raw_buffer_load_b32(ridx, 4u * (uint32_t)(tid + j * NT), zo, 0);
         }
     };
     auto kslot = [&](int p) { return (p - z0 + 2) % 6; };   // index slot of plane p >= z0 - 2
@@ -1043,7 +1035,7 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
         const int q = kslot(p);
 #pragma unroll
         for (int j = 0; j < NE; ++j)
-            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? (int)group_off((uint32_t)v[j], PB) : kSolidOff;
+            if (eok(j)) (&kid[q][0][0])[tid + j * NT] = v[j];
     };
     auto psi_slot = [&](int p) { return (p - z0 + 1) & 3; };   // density slot of plane p >= z0 - 1
 
@@ -1731,6 +1723,24 @@ __global__ void get_pops_kernel(const S *src, const uint32_t *links, const int32
     }
 }
 
+// Index tiles of the step, per tile column col = ty ntx + tx (tiles of
+// tx x ty sites) and plane z: the (tx + 4)(ty + 4) sites around the tile (a
+// ring of two, periodic) in row-major order, each as the byte offset of its
+// population pairs within a buffer half (group_off, pairs of pb bytes) or
+// kSolidOff; planes of a column follow one another.
+__global__ void index_tiles_kernel(const int32_t *idx, int32_t *out, int nx, int ny, int nz, int tx, int ty, int ntx,
+                                   int64_t total, uint32_t pb) {
+    const int hw = tx + 4, per = (tx + 4) * (ty + 4);
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int e = (int)(t % per);
+        const int64_t r = t / per;
+        const int z = (int)(r % nz), col = (int)(r / nz);
+        const int x = wrap((col % ntx) * tx - 2 + e % hw, nx), y = wrap((col / ntx) * ty - 2 + e / hw, ny);
+        const int32_t v = idx[((int64_t)z * ny + y) * nx + x];
+        out[t] = v >= 0 ? (int32_t)group_off((uint32_t)v, pb) : kSolidOff;
+    }
+}
+
 inline int site_grid(int64_t N) {
     const int64_t b = (N + 255) / 256;
     return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
@@ -1743,6 +1753,7 @@ KArgs<S> make_kargs(const StepLaunch &L) {
     a.src = static_cast<const S *>(L.src);
     a.dst = static_cast<S *>(L.dst);
     a.idx = L.idx;
+    a.itab = L.itab;
     a.wstart = L.wstart;
     a.wpos = L.wpos;
     a.nx = L.nx; a.ny = L.ny; a.nz = L.nz;
@@ -1907,6 +1918,15 @@ hipError_t launch_step(int prec, Mode mode, const StepLaunch &L, hipStream_t s) 
 
 hipError_t launch_finalize(const double *partials, int nblocks, double *out, hipStream_t s) {
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_index_tiles(const int32_t *idx, int32_t *itab, int nx, int ny, int nz, int tx, int ty, int pair_bytes,
+                              hipStream_t s) {
+    const int ntx = (nx + tx - 1) / tx, nty = (ny + ty - 1) / ty;
+    const int64_t total = (int64_t)ntx * nty * nz * (tx + 4) * (ty + 4);
+    hipLaunchKernelGGL(index_tiles_kernel, dim3(site_grid(total)), dim3(256), 0, s, idx, itab, nx, ny, nz, tx, ty, ntx,
+                       total, (uint32_t)pair_bytes);
     return hipGetLastError();
 }
 
