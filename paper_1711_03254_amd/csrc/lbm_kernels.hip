@@ -112,7 +112,6 @@ struct KArgs {
     using C = typename Codec<S>::C;
     const S *src;
     S *dst;
-    const int32_t *idx;     // compact index of each lattice site, -1 where solid
     const int32_t *itab;    // index tiles of the step per tile column and plane (index_tiles_kernel)
     const int32_t *wstart;  // work list bounds per tile column and plane
     const uint16_t *wpos;   // work list entries: tile positions of the fluid sites
@@ -1752,7 +1751,6 @@ KArgs<S> make_kargs(const StepLaunch &L) {
     KArgs<S> a;
     a.src = static_cast<const S *>(L.src);
     a.dst = static_cast<S *>(L.dst);
-    a.idx = L.idx;
     a.itab = L.itab;
     a.wstart = L.wstart;
     a.wpos = L.wpos;
