@@ -21,7 +21,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -49,16 +48,10 @@ def workload(n=256, G=-4.2, width=1.5):
 
 
 def kernel_hash():
-    """Hash of the step kernel and of the host code that lays out its data
-    (both decide the traffic the counters saw), over their code lines only:
-    '//' comments and blank lines are left out."""
-    h = hashlib.sha256()
-    for path in (KERNEL_SRC, LAYOUT_SRC):
-        for line in open(path, encoding="utf-8"):
-            code = line.split("//", 1)[0].rstrip()
-            if code:
-                h.update(code.encode() + b"\n")
-    return h.hexdigest()[:16]
+    """Digest of the step kernel and of the host code that lays out its data
+    (both decide the traffic the counters saw), over their code lines only."""
+    from paper_1711_03254_amd.build import source_digest
+    return source_digest()
 
 
 def time_precision(lbm, torch, prec, solid, rA, rB, phys, steps, warmup, check_every):

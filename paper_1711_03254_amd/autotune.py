@@ -79,13 +79,15 @@ def tune_domain(dom: dict, prec: str = "fp32", steps: int = 20, warmup: int = 4,
 
 
 def batch_key(domains: list, prec: str) -> str:
-    """Cache key of a set of domains: precision, count, and a digest of their
-    shapes and solid masks."""
+    """Cache key of a set of domains: precision, count, a digest of their
+    shapes and solid masks, and the digest of the step's source (a timing
+    taken with another kernel does not carry over)."""
+    from .build import source_digest
     h = hashlib.sha256(prec.encode())
     for d in domains:
         h.update(repr(tuple(d["shape"])).encode())
         h.update(np.ascontiguousarray(d["solid"], dtype=np.uint8).tobytes())
-    return f"batch:{prec}:{len(domains)}:{h.hexdigest()[:16]}"
+    return f"batch:{prec}:{len(domains)}:{h.hexdigest()[:16]}:{source_digest()}"
 
 
 def _time_batch(lbm, prec, domains, tile, zchunk, steps, warmup):

@@ -1,6 +1,7 @@
 """Builds the gfx950 shared library liblbm.so in this directory with hipcc."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -22,6 +23,21 @@ HIPCC_FLAGS = [
     # and the batched form), so they all produce the same bits.
     "-ffp-contract=on",
 ]
+
+
+def source_digest() -> str:
+    """Digest of the step kernel source and of the host code that lays out
+    its data and chooses its launch (what a traffic profile or a launch-shape
+    timing depends on), over their code lines only: '//' comments and blank
+    lines are left out.  16 hex digits."""
+    h = hashlib.sha256()
+    for name in ("lbm_kernels.hip", "lbm_api.hip"):
+        with open(os.path.join(CSRC, name), encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
 
 
 def build(verbose: bool = False) -> str:
