@@ -308,6 +308,41 @@ def test_error_paths(lbm):
     assert e.value.code == lbm.LBM_EMASSDRIFT
 
 
+def test_index_tiles_at_the_z_limit(lbm, ora):
+    """A tile column's index tiles are read with 32-bit byte offsets, so
+    nz (tx + 4)(ty + 4) 4 must stay below 4 GiB: with 64 x 16 tiles on a
+    1 x 1 x nz lattice at FP32 (whose population halves allow about 1.5 M
+    such planes), nz = 790 000 is refused (LBM_EINVAL) and nz = 789 000
+    (index-tile offsets up to 4.292e9) steps like any lattice: one step from
+    a seeded random state, 1500 sites of the last planes and 500 anywhere
+    recomputed by the oracle to 1e-5."""
+    per_plane = 4 * (64 + 4) * (16 + 4)
+    bad, good = 790_000, 789_000
+    assert bad * per_plane >= 2 ** 32 > good * per_plane
+    r = np.ones(bad)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_init(lbm.Params(1, 1, bad, prec=lbm.LBM_FP32, rho_init=(r, r.copy()), tile=(64, 16)))
+    assert e.value.code == lbm.LBM_EINVAL and "index tiles" in str(e.value)
+    shape = (good, 1, 1)
+    rA = (0.7 + 0.1 * inputs.uniform(311, good)).reshape(shape)
+    rB = (0.3 + 0.1 * inputs.uniform(312, good)).reshape(shape)
+    phys = dict(tau=(0.8, 1.2), G=-1.0, g=(0.0, 0.0, 1e-5))
+    ctx = lbm.lbm_init(lbm.Params(1, 1, good, prec=lbm.LBM_FP32, rho_init=(rA, rB), tile=(64, 16), check_every=0,
+                                  **phys))
+    p = ora.Params(1, 1, good, **phys)
+    f0 = ora.init(p, rA, rB)
+    lbm.lbm_step(ctx, 1)
+    got_all = lbm.lbm_get_populations(ctx)
+    pick = np.concatenate([good - 1 - (inputs.uniform(313, 1500) * 4000).astype(np.int64),
+                           (inputs.uniform(314, 500) * good).astype(np.int64)])
+    got = got_all.reshape(2, 19, -1)[:, :, pick].transpose(2, 0, 1)
+    want = ora.step_sites(p, f0, pick)
+    dev = nmax(got, want)
+    record("index_tiles_z_limit", nz=good, dev=dev, sites=int(len(pick)))
+    lbm.lbm_free(ctx)
+    assert dev <= TOL["fp32"]
+
+
 def test_device_pointers_and_stream(lbm, ora):
     """Inputs and outputs as torch tensors on the GPU, on a torch stream."""
     import torch
