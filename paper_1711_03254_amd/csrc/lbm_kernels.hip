@@ -967,13 +967,21 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
     constexpr int NT = TX * TY;
     constexpr int RW = TX + 2, RH = TY + 2;     // density tile with its ring
     constexpr int HW = TX + 4, HH = TY + 4;     // index tile with a ring of two
-    constexpr int NE = (HW * HH + NT - 1) / NT; // index-tile entries per thread
+    // The index tile is staged IW entries per load (HW and HH are multiples
+    // of four): 16-byte loads at 16 bits, whose step has the registers to
+    // spare and is limited by its vector memory instructions; single entries
+    // at FP32, whose registers are all in use.
+    constexpr int IW = sizeof(S) == 4 ? 1 : 4;
+    constexpr int NQ = HW * HH / IW;             // loads per plane
+    constexpr int NE = (NQ + NT - 1) / NT;       // loads per thread
+    static_assert(HW * HH % (4 * IW) == 0, "index tiles are staged in whole vectors");
+    using IV = typename std::conditional<IW == 1, uint32_t, u32x4>::type;
     constexpr int NR = 2 * RW + 2 * TY;         // ring sites of the tile
     static_assert(NR <= NT, "the ring must fit in the block");
 
     struct alignas(8) PsiPair { C a, b; };
     __shared__ PsiPair psi[4][RH][RW];
-    __shared__ int kid[6][HH][HW];
+    __shared__ __attribute__((aligned(16))) int kid[6][HH][HW];
     __shared__ double red[NT / 64][6];
     // j_1 + j_2 and both components' second moments of this lane's site of
     // the plane to collide (written by the lane itself one plane earlier)
@@ -1020,21 +1028,25 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
     const __amdgpu_buffer_rsrc_t ridx = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<int32_t *>(a.itab + (size_t)(ty * a.ntx + tx) * (size_t)nz * (HW * HH)), 0,
         (int)(TB * (uint32_t)nz), kRsrcWord3);
-    auto eok = [&](int j) { return (j + 1) * NT <= HW * HH || tid + j * NT < HW * HH; };
-    auto fetch_idx = [&](int zq, int (&v)[NE]) {
+    auto eok = [&](int j) { return (j + 1) * NT <= NQ || tid + j * NT < NQ; };
+    auto fetch_idx = [&](int zq, IV (&v)[NE]) {
         const uint32_t zo = (uint32_t)wrap(zq, nz) * TB;
 #pragma unroll
         for (int j = 0; j < NE; ++j) {
-            v[j] = kSolidOff;
-            if (eok(j)) v[j] = (int)__builtin_amdgcn_raw_buffer_load_b32(ridx, 4u * (uint32_t)(tid + j * NT), zo, 0);
+            v[j] = IV{};
+            if (eok(j)) {
+                const uint32_t off = 4u * IW * (uint32_t)(tid + j * NT);
+                if constexpr (IW == 1) v[j] = __builtin_amdgcn_raw_buffer_load_b32(ridx, off, zo, 0);
+                else v[j] = __builtin_amdgcn_raw_buffer_load_b128(ridx, off, zo, 0);
+            }
         }
     };
     auto kslot = [&](int p) { return (p - z0 + 2) % 6; };   // index slot of plane p >= z0 - 2
-    auto store_idx = [&](int p, const int (&v)[NE]) {
+    auto store_idx = [&](int p, const IV (&v)[NE]) {
         const int q = kslot(p);
 #pragma unroll
-        for (int j = 0; j < NE; ++j)
-            if (eok(j)) (&kid[q][0][0])[tid + j * NT] = v[j];
+        for (int j = 0; j < NE; ++j)   // whole vectors, never split into elements (see pair_load)
+            if (eok(j)) *reinterpret_cast<IV *>(&kid[q][0][0] + IW * (tid + j * NT)) = v[j];
     };
     auto psi_slot = [&](int p) { return (p - z0 + 1) & 3; };   // density slot of plane p >= z0 - 1
 
@@ -1162,7 +1174,7 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
     // ---- prologue: index tiles of planes z0 - 2 .. z0 + 3; planes z0 - 1,
     // z0 and z0 + 1 pulled, one round trip each.
     {
-        int v[6][NE];
+        IV v[6][NE];
 #pragma unroll
         for (int q = 0; q < 6; ++q) fetch_idx(z0 - 2 + q, v[q]);
 #pragma unroll
@@ -1194,7 +1206,7 @@ __device__ __forceinline__ void step_body_pipe(const KArgs<S> &a, int b, int slo
     __builtin_amdgcn_s_waitcnt(0);
 
     const __amdgpu_buffer_rsrc_t dstA = half_rsrc(a.dst, 0, hb), dstB = half_rsrc(a.dst, 1, hb);
-    int vnext[NE];
+    IV vnext[NE];
 
     for (int z = z0; z < z1; ++z) {
         const bool more = z + 2 <= z1;   // plane z + 2 is still needed (for the collision of z + 1)
