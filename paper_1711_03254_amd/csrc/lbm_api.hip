@@ -268,6 +268,7 @@ lbm::StepLaunch make_launch(const lbm_ctx *c, const void *src, void *dst) {
     lbm::StepLaunch L{};
     L.src = src;
     L.dst = dst;
+    L.idx = c->idx;
     L.itab = c->itab;
     L.wstart = c->wstart;
     L.wpos = c->wpos;

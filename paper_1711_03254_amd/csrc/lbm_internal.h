@@ -40,6 +40,7 @@ constexpr int kPartialStride = 8;
 struct StepLaunch {
     const void *src;
     void *dst;
+    const int32_t *idx;     // compact population index of each lattice site, -1 where solid
     const int32_t *itab;    // index tiles of the step (launch_index_tiles) for this tile shape
     const int32_t *wstart;  // work list bounds: per tile column (ty ntx + tx) nz + 1 entries
     const uint16_t *wpos;   // work list entries: tile positions ly tile_x + lx of fluid sites

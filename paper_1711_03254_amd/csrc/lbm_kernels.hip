@@ -112,6 +112,7 @@ struct KArgs {
     using C = typename Codec<S>::C;
     const S *src;
     S *dst;
+    const int32_t *idx;     // compact index of each lattice site, -1 where solid (FP64 step)
     const int32_t *itab;    // index tiles of the step per tile column and plane (index_tiles_kernel)
     const int32_t *wstart;  // work list bounds per tile column and plane
     const uint16_t *wpos;   // work list entries: tile positions of the fluid sites
@@ -554,25 +555,33 @@ __device__ __forceinline__ void step_body(const KArgs<S> &a, int b, int slot) {
         pos = tid < cnt ? (int)a.wpos[w0 + tid] : 0;
     };
 
-    // This tile column's index tiles (index_tiles_kernel): HW HH entries per
-    // plane, planes in order; entry e of a plane is staged by thread e mod NT.
-    constexpr uint32_t TB = 4u * (uint32_t)(HW * HH);   // bytes of one plane's index tile
+    // The index-tile entries this thread stages, gathered from the lattice
+    // index (at 32 x 8 tiles the precomputed per-column tiles hold 1.69
+    // entries per site that neighbouring tiles no longer share through L2;
+    // the gather is 1.4 % faster here): their lattice (x, y).
+    uint32_t exy[NE];
+    bool eok[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        const int e = tid + j * NT;
+        eok[j] = e < HW * HH;
+        const int er = e / HW, ec = e % HW;
+        exy[j] = (uint32_t)wrap(tx * TX - 2 + ec, nx) + (uint32_t)nx * (uint32_t)wrap(ty * TY - 2 + er, ny);
+    }
     const __amdgpu_buffer_rsrc_t ridx = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<int32_t *>(a.itab + (size_t)(ty * a.ntx + tx) * (size_t)nz * (HW * HH)), 0,
-        (int)(TB * (uint32_t)nz), kRsrcWord3);
-    auto eok = [&](int j) { return (j + 1) * NT <= HW * HH || tid + j * NT < HW * HH; };
+        const_cast<int32_t *>(a.idx), 0, (int)(4u * (uint32_t)a.n_sites), kRsrcWord3);
     auto fetch_idx = [&](int zq, int (&v)[NE]) {
-        const uint32_t zo = (uint32_t)wrap(zq, nz) * TB;
+        const uint32_t zo = (uint32_t)wrap(zq, nz) * nxy * 4u;
 #pragma unroll
         for (int j = 0; j < NE; ++j) {
-            v[j] = kSolidOff;
-            if (eok(j)) v[j] = (int)__builtin_amdgcn_raw_buffer_load_b32(ridx, 4u * (uint32_t)(tid + j * NT), zo, 0);
+            v[j] = -1;
+            if (eok[j]) v[j] = (int)__builtin_amdgcn_raw_buffer_load_b32(ridx, exy[j] * 4u, zo, 0);
         }
     };
     auto store_idx = [&](int q, const int (&v)[NE]) {
 #pragma unroll
         for (int j = 0; j < NE; ++j)
-            if (eok(j)) (&kid[q][0][0])[tid + j * NT] = v[j];
+            if (eok[j]) (&kid[q][0][0])[tid + j * NT] = v[j] >= 0 ? (int)group_off((uint32_t)v[j], PB) : kSolidOff;
     };
 
     const __amdgpu_buffer_rsrc_t srcA = half_rsrc(a.src, 0, hb), srcB = half_rsrc(a.src, 1, hb);
@@ -1763,6 +1772,7 @@ KArgs<S> make_kargs(const StepLaunch &L) {
     KArgs<S> a;
     a.src = static_cast<const S *>(L.src);
     a.dst = static_cast<S *>(L.dst);
+    a.idx = L.idx;
     a.itab = L.itab;
     a.wstart = L.wstart;
     a.wpos = L.wpos;
