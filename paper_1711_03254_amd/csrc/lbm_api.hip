@@ -622,8 +622,9 @@ int lbm_init(const lbm_params *pin, lbm_ctx **out) {
         return bail(fail(c, LBM_ENOMEM, "cannot allocate the link mask, index or reduction buffers"));
     if (hipMemcpy(c->idx, idx_h.data(), sizeof(int32_t) * c->N, hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(c, LBM_EDEVICE, "cannot upload the site index"));
-    {
-        // The step reads a tile column's index tiles with 32-bit offsets.
+    if (p.prec != LBM_FP64) {
+        // The 32/16-bit step reads a tile column's index tiles with 32-bit
+        // offsets (the FP64 step gathers from the lattice index instead).
         const int64_t per = (int64_t)(c->tile_x + 4) * (c->tile_y + 4);
         if ((uint64_t)p.nz * (uint64_t)per * 4u >= (1ull << 32))
             return bail(fail(c, LBM_EINVAL, "lattice too long in z for the step's index tiles"));
