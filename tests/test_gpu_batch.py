@@ -43,12 +43,12 @@ CASES = [((40, 24, 24), 1, 1.0, -3.0, 0.2), ((56, 16, 32), 2, 10.0, -3.3, -0.3),
          ((33, 17, 20), 4, 3.0, -3.1, 0.4), ((16, 16, 16), 5, 100.0, -3.0, 0.1)]
 
 
-def make(lbm, prec, case, check_every=0, tile=(32, 8)):
+def make(lbm, prec, case, check_every=0, tile=(32, 8), **kw):
     shape, seed, ratio, G, rs = case
     solid, rA, rB, phys = duct_case(shape, seed, ratio, G, rs)
     nz, ny, nx = shape
     return lbm.lbm_init(lbm.Params(nx, ny, nz, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(rA, rB),
-                                   check_every=check_every, tile=tile, **phys))
+                                   check_every=check_every, tile=tile, **phys, **kw))
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -71,6 +71,28 @@ def test_batch_equals_single_domains(lbm, prec, nsteps):
         lbm.lbm_step(c, 5)
     lbm.lbm_step(singles[0], 3)
     for s, d in zip(singles, batched):
+        assert np.array_equal(lbm.lbm_get_populations(s), lbm.lbm_get_populations(d))
+
+
+@pytest.mark.parametrize("prec", ["fp16s", "bf16s"])
+@pytest.mark.parametrize("tile", [(32, 8), (64, 16)])
+@pytest.mark.parametrize("tau_crit", [0.0, 0.6])
+def test_batch_equals_single_domains_16bit(lbm, prec, tile, tau_crit):
+    """The 16-bit storage forms in a batch (their index tiles staged 16 bytes
+    a load; with tau_crit = 0.6 the instance that forms P_ab in FP64 where
+    tau_mix is below it, here at the A-rich sites, tau_A = 0.56): bit for
+    bit the domains stepped alone, for 7 steps and then 5 more."""
+    singles = [make(lbm, prec, c, tile=tile, tau_crit=tau_crit) for c in CASES]
+    for c in singles:
+        lbm.lbm_step(c, 7)
+    batched = [make(lbm, prec, c, tile=tile, tau_crit=tau_crit) for c in CASES]
+    b = lbm.lbm_batch_create(batched)
+    lbm.lbm_batch_step(b, 7)
+    for s, d in zip(singles, batched):
+        assert np.array_equal(lbm.lbm_get_populations(s), lbm.lbm_get_populations(d))
+    lbm.lbm_batch_step(b, 5)
+    for s, d in zip(singles, batched):
+        lbm.lbm_step(s, 5)
         assert np.array_equal(lbm.lbm_get_populations(s), lbm.lbm_get_populations(d))
 
 
