@@ -498,6 +498,49 @@ def test_full_size_sampled_sites(lbm, ora, packed_spheres, prec):
     del fd
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16s"])
+def test_full_size_all_fluid_sampled_sites(lbm, ora, prec):
+    """The benchmark's all-fluid lattice (256^3, a droplet of A of radius 40
+    in B, no solids, G = -3, tau = 1) at its default launch shape: two
+    steps, 4000 seeded sites (half within two sites of the interface, where
+    the force is largest) recomputed one by one by the oracle; bounds as in
+    the packed-sphere test."""
+    import torch
+    n = 256
+    shape = (n, n, n)
+    rA, rB = inputs.droplet(shape, n / 6.4)
+    solid = np.zeros(shape, np.uint8)
+    phys = dict(tau=(1.0, 1.0), G=-3.0, g=(0.0, 0.0, 0.0), rho_s=0.0)
+    ctx = lbm.lbm_init(lbm.Params(n, n, n, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(rA, rB),
+                                  check_every=100, **phys))
+    tol = {"fp32": TOL["fp32"], "fp16s": 4 * 2.0 ** -11}[prec]
+    p = ora.Params(n, n, n, solid=solid, **phys)
+    z, y, x = np.indices(shape, dtype=np.float64)
+    c = n / 2.0   # the droplet's centre (inputs.droplet)
+    rr = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
+    del x, y, z
+    band = np.flatnonzero(np.abs(rr.ravel() - n / 6.4) < 2.0)
+    del rr
+    pick = np.concatenate([(inputs.uniform(95, 2000) * solid.size).astype(np.int64),
+                           band[(inputs.uniform(96, 2000) * len(band)).astype(np.int64)]])
+    f_prev = ora.init(p, rA, rB)
+    fd = torch.empty((2, 19) + shape, dtype=torch.float64, device="cuda")
+    idx = torch.from_numpy(pick).cuda()
+    for step in range(2):
+        lbm.lbm_step(ctx, 1)
+        lbm.lbm_get_populations(ctx, fd)
+        got = fd.view(2, 19, -1)[:, :, idx].permute(2, 0, 1).cpu().numpy()
+        want = ora.step_sites(p, f_prev, pick)
+        dev = nmax(got, want)
+        record("all_fluid_256_sampled", prec=prec, tile=list(lbm.lbm_info(ctx)["tile"]), step=step + 1, dev=dev,
+               sites=int(len(pick)))
+        assert dev <= tol
+        if step == 0:
+            f_prev = fd.cpu().numpy()
+    del fd
+    lbm.lbm_free(ctx)
+
+
 @pytest.mark.parametrize("prec,nz,zfar", [("fp64", 192, 188), ("fp32", 384, 376)])
 def test_population_offsets_beyond_2_gib(lbm, ora, prec, nz, zfar):
     """A half of the population storage may reach 4 GiB, so byte offsets
