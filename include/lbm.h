@@ -114,10 +114,14 @@ typedef struct {
  * component masses for the periodic check.  On failure *out is NULL.
  * Size limits (LBM_EINVAL): fewer than 2^30 sites, and 11 of the 19
  * directions of the fluid sites' populations below 4 GiB (about 24 M fluid
- * sites at FP64, 48 M at FP32, 97 M with 16-bit storage).  Device memory:
+ * sites at FP64, 48 M at FP32, 97 M with 16-bit storage); with 32- or 16-bit
+ * storage also nz (tile_x + 4)(tile_y + 4) x 4 bytes below 4 GiB (the index
+ * tiles of one tile column: nz < 789 516 at 64 x 16 tiles).  Device memory:
  * two population buffers of about 2 x 22 x n_fluid x storage bytes (the 19
  * directions are stored in two halves of 11 direction slots), plus 8 bytes
- * per site for the link mask and the site index. */
+ * per site for the link mask and the site index, plus at 32 and 16 bits
+ * the step's index tiles, 4 (tile_x + 4)(tile_y + 4) / (tile_x tile_y)
+ * bytes per site of the padded lattice (5.3 at 64 x 16). */
 int lbm_init(const lbm_params *p, lbm_ctx **out);
 
 /* Advances n >= 0 time steps (Eqs. 1-11).  Every check_every steps the step
