@@ -498,6 +498,44 @@ def test_full_size_sampled_sites(lbm, ora, packed_spheres, prec):
     del fd
 
 
+@pytest.mark.parametrize("prec,gpu_kw,ora_kw", [
+    ("fp32", dict(eq_kind=1, wall_kind=1), dict(eq_kind=1, wall_kind=1)),
+    ("fp16s", dict(tau_crit=0.6), {}),
+    ("bf16s", dict(tau_crit=0.6), {})])
+def test_full_size_variants_sampled_sites(lbm, ora, packed_spheres, prec, gpu_kw, ora_kw):
+    """The benchmark workload at its launch shape with the paper's variants:
+    at FP32 the full equilibrium and the momentum-balanced wall force; at 16
+    bits the instance that forms P_ab in FP64 where tau_mix < 0.6 (the A-rich
+    sites, tau_A = 0.55).  One step, 4000 seeded sites (half next to a wall)
+    against the oracle; bounds as in test_full_size_sampled_sites."""
+    import torch
+    solid, rA, rB, phys = packed_spheres
+    n = solid.shape[0]
+    ctx = lbm.lbm_init(lbm.Params(n, n, n, prec=lbm.PRECISIONS[prec], solid=solid, rho_init=(rA, rB),
+                                  check_every=100, **phys, **gpu_kw))
+    tol = {"fp32": TOL["fp32"], "fp16s": 4 * 2.0 ** -11, "bf16s": 4 * 2.0 ** -8}[prec]
+    p = ora.Params(n, n, n, solid=solid, **phys, **ora_kw)
+    fluid = np.flatnonzero(solid.ravel() == 0)
+    near = np.zeros(solid.shape, bool)
+    for ax in range(3):
+        for sh in (1, -1):
+            near |= np.roll(solid, sh, axis=ax) == 1
+    nearwall = np.flatnonzero((solid.ravel() == 0) & near.ravel())
+    pick = np.concatenate([fluid[(inputs.uniform(97, 2000) * len(fluid)).astype(np.int64)],
+                           nearwall[(inputs.uniform(98, 2000) * len(nearwall)).astype(np.int64)]])
+    f0 = ora.init(p, rA, rB)
+    fd = torch.empty((2, 19) + solid.shape, dtype=torch.float64, device="cuda")
+    lbm.lbm_step(ctx, 1)
+    lbm.lbm_get_populations(ctx, fd)
+    got = fd.view(2, 19, -1)[:, :, torch.from_numpy(pick).cuda()].permute(2, 0, 1).cpu().numpy()
+    del fd
+    want = ora.step_sites(p, f0, pick)
+    dev = nmax(got, want)
+    record("packed_spheres_256_variants", prec=prec, kw=gpu_kw, tile=list(lbm.lbm_info(ctx)["tile"]), dev=dev)
+    lbm.lbm_free(ctx)
+    assert dev <= tol
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp16s"])
 def test_full_size_all_fluid_sampled_sites(lbm, ora, prec):
     """The benchmark's all-fluid lattice (256^3, a droplet of A of radius 40
