@@ -32,6 +32,7 @@ struct lbm_ctx {
     double *red_dev = nullptr;
     double *red_host = nullptr;   // pinned
     double *stage = nullptr;      // 5N doubles, allocated on first use
+    double *warm = nullptr;       // 12N doubles of a strain restart, allocated on first use
     double *snap = nullptr;       // 4N doubles: rho1 and u_F of the last lbm_residual (first use)
     bool snap_valid = false;      // false: the snapshot is cleared before the next residual
     hipStream_t stream = nullptr;
@@ -335,11 +336,89 @@ int validate_fields(lbm_ctx *c, const uint8_t *solid_h, const double *r0, const 
     return LBM_OK;
 }
 
-// Copies the field arrays to the device staging buffer (when they are on
-// the host), validates them, and sets the state to their equilibrium, plus
-// (strain) the non-equilibrium part that the velocity field's strain implies.
+// Checks the staged fields (c->stage: rho1, rho2 and, with has_u, u_F) on
+// the device: the verdicts and messages of validate_fields.  Sets
+// c->nfluid.  Synchronizes the stream.
+int check_staged_fields(lbm_ctx *c, bool has_u) {
+    const unsigned long long N = (unsigned long long)c->N;
+    unsigned long long init[3] = {0ull, N, N}, res[3] = {0ull, N, N};
+    auto *out = reinterpret_cast<unsigned long long *>(c->red_dev);   // kPartialStride doubles: room for 3
+    HIPCHK(c, hipMemcpyAsync(out, init, sizeof init, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, lbm::launch_check_fields(c->links, c->stage, c->stage + c->N, has_u ? c->stage + 2 * c->N : nullptr,
+                                       c->N, out, c->stream));
+    HIPCHK(c, hipMemcpyAsync(res, out, sizeof res, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (res[1] < N && res[1] <= res[2]) {
+        double a = 0.0, b = 0.0;
+        HIPCHK(c, hipMemcpy(&a, c->stage + res[1], sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(&b, c->stage + c->N + res[1], sizeof(double), hipMemcpyDeviceToHost));
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "invalid densities at fluid site %lld: rho1=%g rho2=%g (need >= 0, sum > 0)",
+                      (long long)res[1], a, b);
+        return fail(c, LBM_EINVAL, buf);
+    }
+    if (res[2] < N) return fail(c, LBM_EINVAL, "non-finite initial velocity");
+    if (res[0] == 0) return fail(c, LBM_EINVAL, "the lattice has no fluid site");
+    c->nfluid = (int64_t)res[0];
+    return LBM_OK;
+}
+
+// Sets the state from the staged fields: their equilibrium, plus (strain,
+// with u_F) the non-equilibrium part that the velocity field's strain
+// implies and the force shift; then records the masses.
+int staged_to_state(lbm_ctx *c, bool has_u, bool strain) {
+    // Warm start from u_F: the strain's flux Pi / rho (6N) and each
+    // component's force per unit density (6N) in one work buffer, kept for
+    // later restarts.
+    double *pi = nullptr, *acc = nullptr;
+    hipError_t e = hipSuccess;
+    if (strain && has_u) {
+        if (!c->warm && hipMalloc(&c->warm, 12 * sizeof(double) * (size_t)c->N) != hipSuccess) {
+            c->warm = nullptr;
+            (void)hipGetLastError();
+            return fail(c, LBM_ENOMEM, "cannot allocate the 12N-double warm-start buffer");
+        }
+        pi = c->warm;
+        acc = c->warm + 6 * c->N;
+        const double wall0 = c->p.rho_s < 0 ? -c->p.rho_s : 0.0, wall1 = c->p.rho_s > 0 ? c->p.rho_s : 0.0;
+        e = lbm::launch_strain(c->links, c->stage, c->stage + c->N, c->stage + 2 * c->N, c->p.tau[0], c->p.tau[1],
+                               c->p.nx, c->p.ny, c->p.nz, pi, c->stream);
+        if (e == hipSuccess)
+            e = lbm::launch_accel(c->links, c->stage, c->stage + c->N, c->p.G, wall0, wall1, c->p.wall_kind, c->p.g,
+                                  c->p.nx, c->p.ny, c->p.nz, acc, c->stream);
+    }
+    if (e == hipSuccess)
+        e = lbm::launch_init_fields(c->p.prec, c->f[c->cur], c->links, c->idx, c->stage, c->stage + c->N,
+                                    has_u ? c->stage + 2 * c->N : nullptr, pi, acc, c->p.nx, c->p.ny, c->p.nz,
+                                    c->ngroups, c->p.eq_kind, c->ref, c->stream);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("init_fields: ") + hipGetErrorString(e));
+    c->snap_valid = false;
+    int rc = measure(c, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    c->mass0[0] = c->red_host[0];
+    c->mass0[1] = c->red_host[1];
+    return LBM_OK;
+}
+
+// Loads fields into the state.  The first load (lbm_init) checks them on
+// the host, where it also forms the 16-bit shift references from the mean
+// densities; a restart stages them as they are (device inputs device to
+// device) and checks them on the device.
 int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u, int on_device, bool strain = false) {
     const size_t NB = sizeof(double) * (size_t)c->N;
+    int rc = ensure_stage(c);
+    if (rc) return rc;
+    if (c->ref_set) {
+        // device inputs may come from work on other streams
+        if (on_device) HIPCHK(c, hipDeviceSynchronize());
+        const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        HIPCHK(c, hipMemcpyAsync(c->stage, r0, NB, kind, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->stage + c->N, r1, NB, kind, c->stream));
+        if (u) HIPCHK(c, hipMemcpyAsync(c->stage + 2 * c->N, u, 3 * NB, kind, c->stream));
+        rc = check_staged_fields(c, u != nullptr);
+        if (rc) return rc;
+        return staged_to_state(c, u != nullptr, strain);
+    }
     std::vector<double> h0, h1, hu;
     std::vector<uint8_t> hs;
     const double *vr0 = r0, *vr1 = r1, *vu = u;
@@ -361,62 +440,26 @@ int load_fields(lbm_ctx *c, const double *r0, const double *r1, const double *u,
     hs.resize(c->N);
     for (int64_t s = 0; s < c->N; ++s) hs[s] = (uint8_t)(lk[s] & 1u);
     int64_t nf = 0;
-    int rc = validate_fields(c, hs.data(), vr0, vr1, vu, &nf);
+    rc = validate_fields(c, hs.data(), vr0, vr1, vu, &nf);
     if (rc) return rc;
     c->nfluid = nf;
-    if (!c->ref_set) {
-        // 16-bit storage: shift by w_i * rho_ref[a]; default = the mean initial density of the
-        // component over fluid sites (the deviations stay small where a component is in its usual phase).
-        const bool shifted = c->p.prec == LBM_FP16S || c->p.prec == LBM_BF16S;
-        for (int a = 0; a < 2; ++a) {
-            const double *r = a == 0 ? vr0 : vr1;
-            double mean = 0.0;
-            for (int64_t s = 0; s < c->N; ++s)
-                if (!hs[s]) mean += r[s];
-            mean /= (double)nf;
-            const double want = c->p.rho_ref[a];
-            c->ref[a] = !shifted ? 0.0 : (want > 0 ? want : (want < 0 ? 0.0 : mean));
-        }
-        c->ref_set = true;
+    // 16-bit storage: shift by w_i * rho_ref[a]; default = the mean initial density of the
+    // component over fluid sites (the deviations stay small where a component is in its usual phase).
+    const bool shifted = c->p.prec == LBM_FP16S || c->p.prec == LBM_BF16S;
+    for (int a = 0; a < 2; ++a) {
+        const double *r = a == 0 ? vr0 : vr1;
+        double mean = 0.0;
+        for (int64_t s = 0; s < c->N; ++s)
+            if (!hs[s]) mean += r[s];
+        mean /= (double)nf;
+        const double want = c->p.rho_ref[a];
+        c->ref[a] = !shifted ? 0.0 : (want > 0 ? want : (want < 0 ? 0.0 : mean));
     }
-    rc = ensure_stage(c);
-    if (rc) return rc;
+    c->ref_set = true;
     HIPCHK(c, hipMemcpyAsync(c->stage, vr0, NB, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->stage + c->N, vr1, NB, hipMemcpyHostToDevice, c->stream));
     if (vu) HIPCHK(c, hipMemcpyAsync(c->stage + 2 * c->N, vu, 3 * NB, hipMemcpyHostToDevice, c->stream));
-    // Warm start from u_F: the strain's flux Pi / rho (6N) and each
-    // component's force per unit density (6N) in one work buffer.
-    double *work = nullptr, *pi = nullptr, *acc = nullptr;
-    hipError_t e = hipSuccess;
-    if (strain && vu) {
-        if (hipMalloc(&work, 12 * NB) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(c, LBM_ENOMEM, "cannot allocate the 12N-double warm-start buffer");
-        }
-        pi = work;
-        acc = work + 6 * c->N;
-        const double wall0 = c->p.rho_s < 0 ? -c->p.rho_s : 0.0, wall1 = c->p.rho_s > 0 ? c->p.rho_s : 0.0;
-        e = lbm::launch_strain(c->links, c->stage, c->stage + c->N, c->stage + 2 * c->N, c->p.tau[0], c->p.tau[1],
-                               c->p.nx, c->p.ny, c->p.nz, pi, c->stream);
-        if (e == hipSuccess)
-            e = lbm::launch_accel(c->links, c->stage, c->stage + c->N, c->p.G, wall0, wall1, c->p.wall_kind, c->p.g,
-                                  c->p.nx, c->p.ny, c->p.nz, acc, c->stream);
-    }
-    if (e == hipSuccess)
-        e = lbm::launch_init_fields(c->p.prec, c->f[c->cur], c->links, c->idx, c->stage, c->stage + c->N,
-                                    vu ? c->stage + 2 * c->N : nullptr, pi, acc, c->p.nx, c->p.ny, c->p.nz,
-                                    c->ngroups, c->p.eq_kind, c->ref, c->stream);
-    if (work) {
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        (void)hipFree(work);
-    }
-    if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("init_fields: ") + hipGetErrorString(e));
-    c->snap_valid = false;
-    rc = measure(c, nullptr, nullptr, nullptr);
-    if (rc) return rc;
-    c->mass0[0] = c->red_host[0];
-    c->mass0[1] = c->red_host[1];
-    return LBM_OK;
+    return staged_to_state(c, vu != nullptr, strain);
 }
 
 // Order of the positions (ly tx + lx) of a tile plane in storage: its two
@@ -499,7 +542,7 @@ void release(lbm_ctx *c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (void *q : {c->f[0], c->f[1], (void *)c->links, (void *)c->idx, (void *)c->itab, (void *)c->wstart, (void *)c->btab, (void *)c->wpos,
-                    (void *)c->partials, (void *)c->red_dev, (void *)c->stage, (void *)c->snap})
+                    (void *)c->partials, (void *)c->red_dev, (void *)c->stage, (void *)c->warm, (void *)c->snap})
         if (q) (void)hipFree(q);
     if (c->red_host) (void)hipHostFree(c->red_host);
     for (int k = 0; k < 2; ++k) {

@@ -73,6 +73,12 @@ hipError_t launch_index_tiles(const int32_t *idx, int32_t *itab, int nx, int ny,
                               hipStream_t s);
 // Per-site link mask: bit 0 = site solid, bit i = site - c_i solid (periodic).
 hipError_t launch_links(const uint8_t *solid, uint32_t *links, int nx, int ny, int nz, hipStream_t s);
+// Restart field checks (N sites; u 3N or null): out[0] += fluid sites,
+// out[1] = min(out[1], lowest fluid site with invalid densities), out[2] =
+// min(out[2], lowest with a non-finite velocity); the caller sets out to
+// {0, N, N} first.
+hipError_t launch_check_fields(const uint32_t *links, const double *rho0, const double *rho1, const double *u,
+                               int64_t N, unsigned long long *out, hipStream_t s);
 // Internal state from fields: f*_j(x) = f_j(x + c_j) if that site is fluid,
 // else f_opp(j)(x), with f = f_eq from rho (2N), u (3N or null), plus the
 // strain's non-equilibrium part when pi (6N, launch_strain) is given; with

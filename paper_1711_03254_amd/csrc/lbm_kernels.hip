@@ -1761,6 +1761,37 @@ __global__ void index_tiles_kernel(const int32_t *idx, int32_t *out, int nx, int
     }
 }
 
+// Field checks of a restart on the device: counts the fluid sites (bit 0 of
+// the link mask clear) and finds the lowest fluid site whose densities are
+// not finite, negative, or sum to zero or less, and the lowest whose
+// velocity (when given) is not finite.  out[0] += count; out[1], out[2] take
+// the minimum (the caller starts them at N).
+__global__ void check_fields_kernel(const uint32_t *links, const double *r0, const double *r1, const double *u,
+                                    int64_t N, unsigned long long *out) {
+    unsigned long long nf = 0, bad_r = (unsigned long long)N, bad_u = (unsigned long long)N;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N; s += (int64_t)gridDim.x * blockDim.x) {
+        if (links[s] & 1u) continue;
+        ++nf;
+        const double a = r0[s], b = r1[s];
+        if (!(isfinite(a) && isfinite(b) && a >= 0 && b >= 0 && a + b > 0) && (unsigned long long)s < bad_r)
+            bad_r = (unsigned long long)s;
+        if (u && !(isfinite(u[s]) && isfinite(u[N + s]) && isfinite(u[2 * N + s])) && (unsigned long long)s < bad_u)
+            bad_u = (unsigned long long)s;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        nf += __shfl_xor(nf, o, 64);
+        const unsigned long long xr = __shfl_xor(bad_r, o, 64), xu = __shfl_xor(bad_u, o, 64);
+        bad_r = xr < bad_r ? xr : bad_r;
+        bad_u = xu < bad_u ? xu : bad_u;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(out, nf);
+        atomicMin(out + 1, bad_r);
+        atomicMin(out + 2, bad_u);
+    }
+}
+
 inline int site_grid(int64_t N) {
     const int64_t b = (N + 255) / 256;
     return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
@@ -1947,6 +1978,12 @@ hipError_t launch_index_tiles(const int32_t *idx, int32_t *itab, int nx, int ny,
     const int64_t total = (int64_t)ntx * nty * nz * (tx + 4) * (ty + 4);
     hipLaunchKernelGGL(index_tiles_kernel, dim3(site_grid(total)), dim3(256), 0, s, idx, itab, nx, ny, nz, tx, ty, ntx,
                        total, (uint32_t)pair_bytes);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_fields(const uint32_t *links, const double *rho0, const double *rho1, const double *u,
+                               int64_t N, unsigned long long *out, hipStream_t s) {
+    hipLaunchKernelGGL(check_fields_kernel, dim3(site_grid(N)), dim3(256), 0, s, links, rho0, rho1, u, N, out);
     return hipGetLastError();
 }
 

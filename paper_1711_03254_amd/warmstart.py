@@ -156,15 +156,17 @@ def reference(solid, ra0, rb0, phys, steps):
     return ra, u, res
 
 
-def solve_to_accuracy(solid, ra, rb, phys, ref, targets, u=None, prec="fp32", every=500, max_steps=40000):
+def solve_to_accuracy(solid, ra, rb, phys, ref, targets, u=None, prec="fp32", every=500, max_steps=40000,
+                      early=(50, 100, 200, 300, 400)):
     """One solve from (ra, rb) (and, for a warm start, u_F: restart through
     lbm_set_fields_strain; host arrays or device tensors) until its
     distance to the reference (rho_A, u_F) is below each target (eps_u,
-    eps_a) in turn, or max_steps.  The clock runs over the restart and the
-    steps (synchronized per chunk of `every`), not over context creation
-    or the distance checks.  Returns per target the steps and seconds to
-    reach it (None if not reached), the distance trajectory and the final
-    distance."""
+    eps_a) in turn, or max_steps.  The distance is judged after the `early`
+    step counts and then every `every` steps.  The clock runs over the
+    restart and the steps (synchronized per chunk), not over context
+    creation or the distance checks.  Returns per target the steps and
+    seconds to reach it (None if not reached), the distance trajectory and
+    the final distance."""
     ra_h = ra.cpu().numpy().reshape(solid.shape) if isinstance(ra, torch.Tensor) else ra
     rb_h = rb.cpu().numpy().reshape(solid.shape) if isinstance(rb, torch.Tensor) else rb
     ctx = make_context(solid, ra_h, rb_h, phys, prec)
@@ -186,13 +188,15 @@ def solve_to_accuracy(solid, ra, rb, phys, ref, targets, u=None, prec="fp32", ev
                 reached[k] = (steps, secs)
 
     mark(*d0)
+    marks = [e for e in sorted(early) if 0 < e < min(every, max_steps)]
     while steps < max_steps and any(r is None for r in reached):
+        nxt = min(marks.pop(0) if marks else (steps // every + 1) * every, max_steps)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        lbm.lbm_step(ctx, every)
+        lbm.lbm_step(ctx, nxt - steps)
         torch.cuda.synchronize()
         secs += time.perf_counter() - t
-        steps += every
+        steps = nxt
         du, da = lbm.lbm_distance(ctx, ref_a, ref_u)
         traj.append((steps, du, da))
         mark(du, da)

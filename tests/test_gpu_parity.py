@@ -308,6 +308,42 @@ def test_error_paths(lbm):
     assert e.value.code == lbm.LBM_EMASSDRIFT
 
 
+@pytest.mark.parametrize("on_device", [False, True])
+def test_restart_field_checks(lbm, on_device):
+    """A restart (lbm_set_fields after lbm_init) checks its fields on the
+    device with the verdicts of the first load: the lowest fluid site with
+    invalid densities is named with its values (solid sites are not looked
+    at), a non-finite velocity is refused, a refused restart leaves the state
+    as it was, and a valid one goes through; host and device inputs."""
+    import torch
+    shape = (8, 9, 10)
+    nz, ny, nx = shape
+    solid = np.zeros(shape, np.uint8)
+    solid[:, 0, :] = 1
+    r = np.where(solid == 1, 0.0, 1.0)
+    c = lbm.lbm_init(lbm.Params(nx, ny, nz, rho_init=(r, r.copy()), solid=solid, G=-1.0))
+    lbm.lbm_step(c, 3)
+    before = lbm.lbm_get_populations(c)
+    arg = (lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()) if on_device else (lambda x: x)
+    bad = r.copy()
+    bad.ravel()[700] = np.nan
+    bad.ravel()[500] = -0.5           # fluid (y = 5): the lowest invalid site
+    bad[solid == 1] = -7.0            # solid sites are not checked
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_set_fields(c, arg(bad), arg(r.copy()))
+    assert e.value.code == lbm.LBM_EINVAL
+    assert "fluid site 500:" in str(e.value) and "rho1=-0.5" in str(e.value)
+    u = np.zeros((3,) + shape)
+    u[1].ravel()[300] = np.inf
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_set_fields(c, arg(r.copy()), arg(r.copy()), arg(u))
+    assert e.value.code == lbm.LBM_EINVAL and "non-finite initial velocity" in str(e.value)
+    assert np.array_equal(lbm.lbm_get_populations(c), before)
+    lbm.lbm_set_fields(c, arg(r.copy()), arg(r.copy()))
+    assert lbm.lbm_info(c)["n_fluid"] == int((solid == 0).sum())
+    lbm.lbm_free(c)
+
+
 def test_index_tiles_at_the_z_limit(lbm, ora):
     """A tile column's index tiles are read with 32-bit byte offsets, so
     nz (tx + 4)(ty + 4) 4 must stay below 4 GiB: with 64 x 16 tiles on a
