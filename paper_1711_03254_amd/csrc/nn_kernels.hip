@@ -9,6 +9,8 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/lbm.h"
 #include "../../include/lbm_nn.h"
 
@@ -32,19 +34,23 @@ __device__ __forceinline__ s16x4 load4(const uint16_t *p) {
 
 // ---------------------------------------------------------------------------
 // Forward convolution.  GEMM view: out[co][p] = sum_k A[co][k] B[k][p] with
-// k = (t, ci).  A wave computes 16 output channels x 64 positions as four
-// 16 x 16 tiles that share the A operand (the weights of one tap and 16 input
-// channels); a block is four waves along positions.  Operand layout of the
-// 16x16x16 instruction: lane l supplies A[l % 16][4 (l / 16) + j] and
+// k = (t, ci).  A wave computes CT groups of 16 output channels x 64
+// positions, as CT x 4 16 x 16 tiles: each B operand (16 input channels of 16
+// positions at one tap) is loaded once and used by the CT groups, each A
+// operand (the weights of one tap and 16 input channels) by the four
+// position tiles; a block is four waves along positions.  Operand layout of
+// the 16x16x16 instruction: lane l supplies A[l % 16][4 (l / 16) + j] and
 // B[4 (l / 16) + j][l % 16] (j = 0..3) and receives D[4 (l / 16) + j][l % 16].
+// Every output sums its taps and input channels in the same order whatever
+// CT is.
 // ---------------------------------------------------------------------------
-template <bool OUT_F32>
+template <bool OUT_F32, int CT>
 __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict__ x, int ldx,
                                                      const uint16_t *__restrict__ w, const float *__restrict__ bias,
                                                      void *__restrict__ y, int ldy, int relu, int nb, int D, int H,
                                                      int W, int ci, int co) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int co0 = blockIdx.y * 16;
+    const int co0 = blockIdx.y * 16 * CT;
     const int64_t P = (int64_t)nb * D * H * W;
     const int64_t pbase = (int64_t)blockIdx.x * 256 + wv * 64;
     const int col = lane & 15, kq = 4 * (lane >> 4);
@@ -61,9 +67,11 @@ __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict_
         pz[f] = (int)(q % D);
         pb[f] = (int)(q / D);
     }
-    f32x4 acc[4];
+    f32x4 acc[CT][4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) acc[f] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < CT; ++g)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc[g][f] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     const s16x4 zero4 = {0, 0, 0, 0};
     for (int t = 0; t < 27; ++t) {
@@ -77,34 +85,41 @@ __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict_
         }
         const uint16_t *wa = w + ((int64_t)t * co + co0 + col) * ci + kq;
         for (int c0 = 0; c0 < ci; c0 += 16) {
-            const s16x4 a = load4(wa + c0);
+            s16x4 b[4];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                const s16x4 b = valid[f] ? load4(src[f] + c0) : zero4;
-                acc[f] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[f], 0, 0, 0);
+            for (int f = 0; f < 4; ++f) b[f] = valid[f] ? load4(src[f] + c0) : zero4;
+#pragma unroll
+            for (int g = 0; g < CT; ++g) {
+                const s16x4 a = load4(wa + (int64_t)16 * g * ci + c0);
+#pragma unroll
+                for (int f = 0; f < 4; ++f) acc[g][f] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[f], acc[g][f], 0, 0, 0);
             }
         }
     }
-    // lane holds channels co0 + kq + j of position pbase + 16 f + col
-    float bj[4];
+    // lane holds channels co0 + 16 g + kq + j of position pbase + 16 f + col
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bj[j] = bias ? bias[co0 + kq + j] : 0.f;
+    for (int g = 0; g < CT; ++g) {
+        const int cg = co0 + 16 * g + kq;
+        float bj[4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        if (!valid[f]) continue;
-        const int64_t p = pbase + 16 * f + col;
-        float v[4];
+        for (int j = 0; j < 4; ++j) bj[j] = bias ? bias[cg + j] : 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            v[j] = acc[f][j] + bj[j];
-            if (relu) v[j] = v[j] > 0.f ? v[j] : 0.f;
-        }
-        if constexpr (OUT_F32) {
-            *reinterpret_cast<float4 *>(static_cast<float *>(y) + p * ldy + co0 + kq) = float4{v[0], v[1], v[2], v[3]};
-        } else {
-            const uint32_t lo = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
-            const uint32_t hi = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
-            *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(y) + p * ldy + co0 + kq) = uint2{lo, hi};
+        for (int f = 0; f < 4; ++f) {
+            if (!valid[f]) continue;
+            const int64_t p = pbase + 16 * f + col;
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v[j] = acc[g][f][j] + bj[j];
+                if (relu) v[j] = v[j] > 0.f ? v[j] : 0.f;
+            }
+            if constexpr (OUT_F32) {
+                *reinterpret_cast<float4 *>(static_cast<float *>(y) + p * ldy + cg) = float4{v[0], v[1], v[2], v[3]};
+            } else {
+                const uint32_t lo = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+                const uint32_t hi = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+                *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(y) + p * ldy + cg) = uint2{lo, hi};
+            }
         }
     }
 }
@@ -454,13 +469,27 @@ int nn_conv3d_fwd(const uint16_t *x, int32_t ldx, const uint16_t *w, const float
         ldy < co || ldx % 4 || ldy % 4 || !aligned8(x) || !aligned8(w) || (y_fp32 ? ((uintptr_t)y & 15) : !aligned8(y)))
         return LBM_EINVAL;
     const int64_t P = positions(nb, d, h, w_);
-    const dim3 grid((unsigned)((P + 255) / 256), (unsigned)(co / 16));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (y_fp32)
-        hipLaunchKernelGGL(conv3d_kernel<true>, grid, dim3(256), 0, s, x, ldx, w, bias, y, ldy, relu, nb, d, h, w_, ci, co);
-    else
-        hipLaunchKernelGGL(conv3d_kernel<false>, grid, dim3(256), 0, s, x, ldx, w, bias, y, ldy, relu, nb, d, h, w_, ci,
-                           co);
+    // CT groups of 16 output channels per wave: the largest of 6, 4, 3, 2, 1
+    // that divides co / 16.
+    const int groups = co / 16;
+    const int ct = groups % 6 == 0 ? 6 : groups % 4 == 0 ? 4 : groups % 3 == 0 ? 3 : groups % 2 == 0 ? 2 : 1;
+    const dim3 grid((unsigned)((P + 255) / 256), (unsigned)(groups / ct));
+    auto launch = [&](auto out_f32, auto ctc) {
+        hipLaunchKernelGGL((conv3d_kernel<decltype(out_f32)::value, decltype(ctc)::value>), grid, dim3(256), 0, s, x,
+                           ldx, w, bias, y, ldy, relu, nb, d, h, w_, ci, co);
+    };
+    auto by_ct = [&](auto out_f32) {
+        switch (ct) {
+        case 6: launch(out_f32, std::integral_constant<int, 6>{}); break;
+        case 4: launch(out_f32, std::integral_constant<int, 4>{}); break;
+        case 3: launch(out_f32, std::integral_constant<int, 3>{}); break;
+        case 2: launch(out_f32, std::integral_constant<int, 2>{}); break;
+        default: launch(out_f32, std::integral_constant<int, 1>{}); break;
+        }
+    };
+    if (y_fp32) by_ct(std::true_type{});
+    else by_ct(std::false_type{});
     return done();
 }
 

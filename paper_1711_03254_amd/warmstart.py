@@ -211,15 +211,19 @@ def compare(net, case, phys, ref, targets, precs=("fp32", "fp16s"), every=500, m
     (device rho_A, u_F): the cold start, the cold fields restarted
     consistently (u_F = 0), the network's velocity on the cold densities,
     and the network's velocity and densities.  A warm solve's seconds
-    include the prediction (features on the host, the network on the GPU,
-    the restart).  Returns per precision every solve, the prediction's own
-    distance to the reference, and per target the steps and time factors
-    cold / other (None where a solve did not reach the target)."""
+    include the prediction (features, the network and the decoding on the
+    GPU from the cold fields already in device memory, and the restart).
+    Returns per precision every solve, the prediction's own distance to the
+    reference, and per target the steps and time factors cold / other (None
+    where a solve did not reach the target)."""
     solid, ra0, rb0 = case["solid"], case["ra0"], case["rb0"]
-    warm_state(net, solid, ra0, rb0, phys)    # first call: allocations
+    solid_d = torch.from_numpy(np.ascontiguousarray(solid, np.uint8)).cuda()
+    ra0_d = torch.from_numpy(np.ascontiguousarray(ra0, np.float64)).cuda()
+    rb0_d = torch.from_numpy(np.ascontiguousarray(rb0, np.float64)).cuda()
+    warm_state(net, solid_d, ra0_d, rb0_d, phys)    # first call: allocations
     torch.cuda.synchronize()
     t = time.perf_counter()
-    u, ra, rb = warm_state(net, solid, ra0, rb0, phys)
+    u, ra, rb = warm_state(net, solid_d, ra0_d, rb0_d, phys)
     torch.cuda.synchronize()
     t_pred = time.perf_counter() - t
     fluid = solid == 0
@@ -235,8 +239,6 @@ def compare(net, case, phys, ref, targets, precs=("fp32", "fp16s"), every=500, m
                "u": 1.0, "rho_a": float(np.linalg.norm((ra0 - ref_a)[fluid]) / np.linalg.norm(ref_a[fluid]))},
            "targets": [list(t) for t in targets]}
     zero = torch.zeros_like(u)
-    ra0_d = torch.from_numpy(np.ascontiguousarray(ra0, np.float64)).cuda()
-    rb0_d = torch.from_numpy(np.ascontiguousarray(rb0, np.float64)).cuda()
     for prec in precs:
         arms = {
             # the method's own start: f_eq(rho0, 0) (lbm_init)
