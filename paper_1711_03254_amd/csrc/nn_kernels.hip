@@ -124,6 +124,94 @@ __global__ void __launch_bounds__(256) conv3d_kernel(const uint16_t *__restrict_
     }
 }
 
+// The same convolution for lattices whose rows hold a multiple of 64 sites
+// and whose planes a multiple of 4 rows: a block owns 64 x 4 positions of
+// one plane (wave w: row w, four tiles of 16 positions) and CT groups of 16
+// output channels.  Per chunk of 16 input channels it stages in LDS the
+// 3 x 6 x 66 sites around its positions (periodic), and every tap reads its
+// B operands from there; each output sums the chunks in order, within a
+// chunk the taps in order.
+constexpr int kLx = 66, kLy = 6, kLz = 3, kLvox = kLx * kLy * kLz;
+
+template <bool OUT_F32, int CT>
+__global__ void __launch_bounds__(256) conv3d_lds_kernel(const uint16_t *__restrict__ x, int ldx,
+                                                         const uint16_t *__restrict__ w,
+                                                         const float *__restrict__ bias, void *__restrict__ y,
+                                                         int ldy, int relu, int D, int H, int W, int ci, int co) {
+    __shared__ __attribute__((aligned(16))) uint16_t halo[kLvox * 16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int co0 = blockIdx.y * 16 * CT;
+    const int xt = W / 64, yt = H / 4;
+    int q = blockIdx.x;
+    const int x0 = (q % xt) * 64;
+    q /= xt;
+    const int y0 = (q % yt) * 4;
+    q /= yt;
+    const int z = q % D, b = q / D;
+    const int col = lane & 15, kq = 4 * (lane >> 4);
+
+    f32x4 acc[CT][4];
+#pragma unroll
+    for (int g = 0; g < CT; ++g)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc[g][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int c0 = 0; c0 < ci; c0 += 16) {
+        __syncthreads();   // the previous chunk's reads are done
+        for (int piece = threadIdx.x; piece < 2 * kLvox; piece += 256) {
+            const int v = piece >> 1, half = piece & 1;
+            const int lz = v / (kLx * kLy), ly = (v / kLx) % kLy, lx = v % kLx;
+            const int gz = wrapi(z + lz - 1, D), gy = wrapi(y0 + ly - 1, H), gx = wrapi(x0 + lx - 1, W);
+            const int64_t site = (((int64_t)b * D + gz) * H + gy) * W + gx;
+            *reinterpret_cast<uint4 *>(halo + v * 16 + 8 * half) =
+                *reinterpret_cast<const uint4 *>(x + site * ldx + c0 + 8 * half);
+        }
+        __syncthreads();
+        for (int t = 0; t < 27; ++t) {
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;   // offsets + 1
+            s16x4 bv[4];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int v = (dz * kLy + wv + dy) * kLx + 16 * f + col + dx;
+                bv[f] = __builtin_bit_cast(s16x4, *reinterpret_cast<const uint2 *>(halo + v * 16 + kq));
+            }
+            const uint16_t *wa = w + ((int64_t)t * co + co0 + col) * ci + c0 + kq;
+#pragma unroll
+            for (int g = 0; g < CT; ++g) {
+                const s16x4 a = load4(wa + (int64_t)16 * g * ci);
+#pragma unroll
+                for (int f = 0; f < 4; ++f) acc[g][f] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv[f], acc[g][f], 0, 0, 0);
+            }
+        }
+    }
+    // lane holds channels co0 + 16 g + kq + j of position (x0 + 16 f + col, y0 + wv)
+    const int64_t prow = (((int64_t)b * D + z) * H + y0 + wv) * W + x0;
+#pragma unroll
+    for (int g = 0; g < CT; ++g) {
+        const int cg = co0 + 16 * g + kq;
+        float bj[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bj[j] = bias ? bias[cg + j] : 0.f;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int64_t p = prow + 16 * f + col;
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v[j] = acc[g][f][j] + bj[j];
+                if (relu) v[j] = v[j] > 0.f ? v[j] : 0.f;
+            }
+            if constexpr (OUT_F32) {
+                *reinterpret_cast<float4 *>(static_cast<float *>(y) + p * ldy + cg) = float4{v[0], v[1], v[2], v[3]};
+            } else {
+                const uint32_t lo = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+                const uint32_t hi = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+                *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(y) + p * ldy + cg) = uint2{lo, hi};
+            }
+        }
+    }
+}
+
 __global__ void flip_kernel(const uint16_t *w, uint16_t *wt, int ci, int co) {
     const int64_t n = 27LL * ci * co;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
@@ -475,9 +563,17 @@ int nn_conv3d_fwd(const uint16_t *x, int32_t ldx, const uint16_t *w, const float
     const int groups = co / 16;
     const int ct = groups % 6 == 0 ? 6 : groups % 4 == 0 ? 4 : groups % 3 == 0 ? 3 : groups % 2 == 0 ? 2 : 1;
     const dim3 grid((unsigned)((P + 255) / 256), (unsigned)(groups / ct));
+    // rows of a multiple of 64 sites, planes of a multiple of 4 rows, and
+    // 16-byte aligned input rows: the LDS-staged form
+    const bool staged = w_ % 64 == 0 && h % 4 == 0 && ldx % 8 == 0 && ((uintptr_t)x & 15) == 0;
+    const dim3 sgrid((unsigned)((int64_t)nb * d * (h / 4) * (w_ / 64)), (unsigned)(groups / ct));
     auto launch = [&](auto out_f32, auto ctc) {
-        hipLaunchKernelGGL((conv3d_kernel<decltype(out_f32)::value, decltype(ctc)::value>), grid, dim3(256), 0, s, x,
-                           ldx, w, bias, y, ldy, relu, nb, d, h, w_, ci, co);
+        if (staged)
+            hipLaunchKernelGGL((conv3d_lds_kernel<decltype(out_f32)::value, decltype(ctc)::value>), sgrid, dim3(256), 0,
+                               s, x, ldx, w, bias, y, ldy, relu, d, h, w_, ci, co);
+        else
+            hipLaunchKernelGGL((conv3d_kernel<decltype(out_f32)::value, decltype(ctc)::value>), grid, dim3(256), 0, s,
+                               x, ldx, w, bias, y, ldy, relu, nb, d, h, w_, ci, co);
     };
     auto by_ct = [&](auto out_f32) {
         switch (ct) {
